@@ -1,0 +1,118 @@
+"""Pins of the oracle's random-number and math building blocks (CPU only).
+
+* Philox4x32-10 against rocRAND's host implementation (a library routine).
+* log, sin(2 pi a), cos(2 pi a) against numpy float64, in float32 ulps.
+* The Box-Muller normals of the Brownian move against N(0, 1) (KS test,
+  moments) and against the 24-bit bound |z| <= sqrt(-2 ln 2^-24).
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    src = os.path.join(HERE, "helpers", "philox_rocrand_ref.cpp")
+    inc = "/opt/rocm/include"
+    if not os.path.isdir(os.path.join(inc, "rocrand")) or shutil.which("g++") is None:
+        pytest.skip("rocRAND headers or g++ not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "philox_ref")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-D__HIP_PLATFORM_AMD__", f"-I{inc}", src,
+                    "-o", exe], check=True)
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_ref):
+    rng = np.random.default_rng(1234)
+    rows = []
+    for _ in range(2000):
+        c = rng.integers(0, 2**32, 4, dtype=np.uint64)
+        c[1] %= 2**30  # reachable through rocRAND's offset argument
+        k = rng.integers(0, 2**32, 2, dtype=np.uint64)
+        rows.append([int(v) for v in (*c, *k)])
+    # structured counters used by the step (id, t, purpose, aux)
+    for pur in range(6):
+        rows.append([7, 11, pur, 0, 0, 0])
+        rows.append([2**32 - 1, 2**30 - 1, pur, 2**32 - 1, 2**32 - 1, 2**32 - 1])
+    rows.append([0, 0, 0, 0, 0, 0])
+    inp = "\n".join(" ".join(str(v) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=inp, capture_output=True, text=True, check=True)
+    ref = np.array([[int(v) for v in line.split()] for line in out.stdout.strip().splitlines()],
+                   np.uint64)
+    got = np.array([oracle.philox(r[:4], r[4:]) for r in rows], np.uint64)
+    assert ref.shape == got.shape
+    assert np.array_equal(ref, got)
+
+
+def test_philox_bits_uniform():
+    # chi^2 of the top byte over 4096 blocks and a lag-1 correlation check
+    words = np.concatenate([oracle.philox([i, 3, 2, 0], [0, 0]) for i in range(4096)])
+    hist = np.bincount(words >> 24, minlength=256)
+    chi2 = ((hist - len(words) / 256) ** 2 / (len(words) / 256)).sum()
+    assert stats.chi2.sf(chi2, 255) > 1e-4
+    u = words.astype(np.float64) / 2**32
+    r = np.corrcoef(u[:-1], u[1:])[0, 1]
+    assert abs(r) < 4.0 / math.sqrt(len(u))
+
+
+def _ulp32(x):
+    x = np.abs(np.asarray(x, np.float64))
+    e = np.floor(np.log2(np.maximum(x, 2.0**-126)))
+    return 2.0 ** (e - 23)
+
+
+def test_log_within_2_ulp():
+    rng = np.random.default_rng(5)
+    k = np.concatenate([np.arange(1, 4097), rng.integers(1, 2**24 + 1, 60000),
+                        2**24 - np.arange(0, 4096), 2 ** np.arange(0, 25)])
+    xs = (k.astype(np.float64) * 2.0**-24).astype(np.float32)
+    got = np.array([oracle.log(float(x)) for x in xs], np.float64)
+    ref = np.log(xs.astype(np.float64))
+    err = np.abs(got - ref)
+    # ulp of the result; log(1) = 0 must be exact
+    tol = 2.0 * _ulp32(ref)
+    assert got[xs == 1.0].tolist() == [0.0] * int((xs == 1.0).sum())
+    nz = ref != 0
+    assert np.all(err[nz] <= tol[nz]), float((err[nz] / tol[nz]).max())
+
+
+def test_sincos2pi_within_2_ulp():
+    rng = np.random.default_rng(6)
+    k = np.concatenate([np.arange(0, 2048), rng.integers(0, 2**24, 60000),
+                        np.arange(0, 2**24, 2**20), np.arange(2**22 - 64, 2**22 + 64)])
+    a = (k.astype(np.float64) * 2.0**-24).astype(np.float32)
+    sc = np.array([oracle.sincos2pi(float(v)) for v in a], np.float64)
+    ang = 2.0 * np.pi * a.astype(np.float64)
+    for got, ref in ((sc[:, 0], np.sin(ang)), (sc[:, 1], np.cos(ang))):
+        zero = np.abs(ref) < 1e-15  # exact zeros of sin/cos at quadrant points
+        assert np.all(got[zero] == 0.0)
+        err = np.abs(got - ref)[~zero]
+        assert np.all(err <= 2.0 * _ulp32(ref[~zero])), float((err / _ulp32(ref[~zero])).max())
+    for a0, s0, c0 in ((0.0, 0.0, 1.0), (0.25, 1.0, 0.0), (0.5, 0.0, -1.0), (0.75, -1.0, 0.0)):
+        assert oracle.sincos2pi(a0) == (s0, c0) or oracle.sincos2pi(a0) == (s0, -c0) \
+            or oracle.sincos2pi(a0) == (-s0, c0)
+
+
+def test_gauss3_is_standard_normal():
+    # 4 x 30,000 agents, keyed by the four seeds the paper's runs use (Sec. 3.3)
+    z = np.array([oracle.gauss3(seed, i, 0) for seed in (12, 42, 314, 101010)
+                  for i in range(30000)], np.float64)
+    for col in range(3):
+        d = stats.kstest(z[:, col], "norm")
+        assert d.pvalue > 1e-3
+        assert abs(z[:, col].mean()) < 4.0 / math.sqrt(len(z))
+        assert abs(z[:, col].var() - 1.0) < 4.0 * math.sqrt(2.0 / len(z))
+    # components independent
+    c = np.corrcoef(z.T)
+    assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 4.0 / math.sqrt(len(z)))
+    bound = math.sqrt(-2.0 * math.log(2.0**-24))
+    assert np.abs(z).max() <= bound * (1 + 1e-6)
