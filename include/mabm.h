@@ -1,0 +1,199 @@
+/*
+ * mabm.h -- C ABI of the MI355X (gfx950) molecule-agent step library.
+ *
+ * The library advances a molecule-level agent-based simulation of a
+ * signalling pathway (Maestri, "Towards In Silico Cancer Therapy Design",
+ * Abstract and Sec. 2): every molecule is an agent with a species, an id and
+ * a position in a 3D volume.  One step moves every agent by a Brownian
+ * displacement, finds reaction partners by spatial proximity, fires binding,
+ * catalysis, unbinding, translocation, emission and degradation rules, and
+ * compacts births and deaths.  The exact step definition (random-number
+ * layout, boundaries, claim rule, placement of products) is the one written
+ * out in the design notes as O0..O10; every call below names the paper
+ * passage whose input or output it carries.
+ *
+ * Conventions for every call:
+ *   - Return value: mabm_status, 0 = MABM_OK, negative = error.  No call
+ *     aborts or throws; mabm_last_error() gives a message.
+ *   - Pointers named device_* are HIP device pointers; every other pointer
+ *     is host memory owned by the caller and only read/written during the
+ *     call.
+ *   - Device memory: the library allocates none.  The caller passes one
+ *     device arena of at least mabm_arena_bytes() bytes and a HIP stream;
+ *     both are borrowed and must outlive the simulation.
+ *   - Steps are enqueued asynchronously on the stream; mabm_counts and
+ *     mabm_export synchronise it.  Device-side failures (capacity overflow,
+ *     placement failure) are sticky: they are reported by the next
+ *     synchronising call, after which only mabm_destroy_sim and
+ *     mabm_last_error are valid.
+ *   - One simulation must not be used from two host threads at once;
+ *     distinct simulations are independent.
+ */
+#ifndef MABM_H
+#define MABM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MABM_ABI_VERSION 1u
+#define MABM_MAX_SPECIES 64
+#define MABM_MAX_RULES 255
+#define MABM_NONE 0xFFFFFFFFu
+
+typedef enum {
+    MABM_OK = 0,
+    MABM_E_INVALID = -1,  /* bad argument or inconsistent model            */
+    MABM_E_STATE = -2,    /* call not allowed in this state                 */
+    MABM_E_NOMEM = -3,    /* arena too small                                */
+    MABM_E_CAPACITY = -4, /* more live agents (or births) than the capacity */
+    MABM_E_DEVICE = -5    /* HIP runtime error or device-side failure       */
+} mabm_status;
+
+/* Simulated volume (Sec. 2 footnote: simulation volume, compartments).
+ * PERIODIC_BOX: cube [0, box_um)^3 with periodic wrap, one compartment 0.
+ * SPHERE: ball of outer_radius_um at the origin, one compartment 0.
+ * NESTED_SPHERES: nucleus (compartment 0, |p| < inner_radius_um) inside a
+ * cell (compartment 1, inner <= |p| <= outer_radius_um). */
+typedef enum { MABM_PERIODIC_BOX = 0, MABM_SPHERE = 1, MABM_NESTED_SPHERES = 2 } mabm_geometry;
+
+typedef enum { MABM_BIMOL = 0, MABM_UNIMOL = 1 } mabm_rule_kind;
+
+/* Placement of a rule's products (Abstract: binding, release of reaction
+ * products, migration between compartments; Sec. 2: expressors).
+ * KEEP: products replace the reactants in place (binding, catalysis,
+ *       conversion, degradation when the product is -1).
+ * SPLIT: unimolecular A -> P1 + P2, P1 at p+u and P2 at p-u, u uniform in
+ *       the ball of release_radius_um (unbinding).
+ * EMIT: unimolecular A -> A (or P1) + child P2 at p+u (expression).
+ * TRANSLOCATE: unimolecular crossing of the nuclear membrane from from_comp
+ *       to to_comp, landing release_radius_um across it, radially. */
+typedef enum { MABM_KEEP = 0, MABM_SPLIT = 1, MABM_EMIT = 2, MABM_TRANSLOCATE = 3 } mabm_placement;
+
+typedef struct {
+    uint32_t abi_version;  /* MABM_ABI_VERSION */
+    int32_t geometry;      /* mabm_geometry */
+    float box_um;          /* PERIODIC_BOX side, um */
+    float outer_radius_um; /* SPHERE / NESTED_SPHERES outer radius, um */
+    float inner_radius_um; /* NESTED_SPHERES nucleus radius, um */
+    float dt_s;            /* time step, s (> 0) */
+    uint64_t seed;         /* Philox key */
+    uint32_t capacity;     /* maximum live agents at any step end */
+    float cell_um;         /* spatial-hash cell size, um; 0 = chosen by the library */
+    uint32_t flags;        /* MABM_FLAG_* */
+} mabm_config;
+
+/* Record, for every live agent, the cell id, unimolecular event and partner
+ * of the last step, so that mabm_export can return them.  Costs extra
+ * traffic; results are identical with and without it. */
+#define MABM_FLAG_RECORD 1u
+
+/* Per-step rule (Sec. 2: "reactions it participates in, including
+ * interacting partners, rates, and resulting products").  Species are ids
+ * returned by mabm_add_species; -1 = none.
+ * BIMOL: reactant[0] is the claimer, reactant[1] the target; on contact
+ *   (centre distance <= radius_um, same compartment) the pair fires with
+ *   probability prob_per_step; claimer -> product[0], target -> product[1]
+ *   (-1 = the agent is consumed).  placement must be KEEP.  At most one
+ *   BIMOL rule per unordered species pair.
+ * UNIMOL: reactant[0] fires with probability prob_per_step per step when in
+ *   from_comp (-1 = any compartment); the probabilities of one species'
+ *   rules in one compartment must sum to <= 1. */
+typedef struct {
+    int32_t kind;             /* mabm_rule_kind */
+    int32_t reactant[2];
+    int32_t product[2];
+    float radius_um;          /* BIMOL contact radius */
+    double prob_per_step;     /* in [0, 1] */
+    int32_t placement;        /* mabm_placement */
+    float release_radius_um;  /* SPLIT/EMIT ball radius; TRANSLOCATE offset (>= 1e-3) */
+    int32_t from_comp, to_comp;
+} mabm_rule;
+
+/* Device bytes a simulation with this configuration needs (an upper bound
+ * independent of the model's species and rules beyond the stated counts).
+ * Used for admission by HBM footprint.  Returns 0 for an invalid config. */
+size_t mabm_arena_bytes(const mabm_config* cfg, uint32_t n_species, uint32_t n_rules);
+
+/* Create a simulation in the caller's device arena, working on the caller's
+ * HIP stream (a hipStream_t, NULL = the null stream).  The arena is carved,
+ * not cleared beyond what the library needs.  *out receives an opaque handle
+ * owned by the caller (free with mabm_destroy_sim).
+ * Errors: E_INVALID (config), E_NOMEM (arena_bytes too small), E_DEVICE. */
+typedef struct mabm_sim mabm_sim;
+mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t arena_bytes,
+                            void* hip_stream, mabm_sim** out);
+
+/* Add a species (Sec. 2: molecular species with diffusion from
+ * Stokes-Einstein, initial concentration -> count, localisation ->
+ * compartment).  Ids 0, 1, ... in call order.  E_STATE after the model is
+ * finalized (first step/counts/export/import). */
+mabm_status mabm_add_species(mabm_sim* sim, const char* name, float diffusion_um2_s,
+                             uint32_t initial_count, int32_t compartment, int32_t* out_species_id);
+
+/* Add a rule; validated at once (unknown species, probability outside
+ * [0,1], bad placement or compartments, a second BIMOL rule for a pair:
+ * E_INVALID).  Ids 0, 1, ... in call order. */
+mabm_status mabm_add_rule(mabm_sim* sim, const mabm_rule* rule, int32_t* out_rule_id);
+
+/* Cells per axis and cell size the simulation uses (after finalize). */
+mabm_status mabm_grid(mabm_sim* sim, uint32_t* cells_per_axis, float* cell_um);
+
+/* Enqueue n_steps steps on the stream; returns without synchronising.  The
+ * first call finalizes the model: consistency checks of Sec. 2 (probability
+ * sums, radii against the cell size: E_INVALID), table upload and initial
+ * placement. */
+mabm_status mabm_step(mabm_sim* sim, uint32_t n_steps);
+
+/* Per-species counts of live agents after the last enqueued step (Sec. 2:
+ * concentrations over time; out has n_species entries) and the step
+ * counter.  Synchronises the stream; reports sticky device errors. */
+mabm_status mabm_counts(mabm_sim* sim, uint64_t* out, uint32_t n_species, uint64_t* out_step);
+
+/* Number of live agents and the next id to be assigned (synchronises). */
+mabm_status mabm_size(mabm_sim* sim, uint32_t* n_live, uint32_t* next_id);
+
+/* Copy the live agents to host arrays of capacity >= n_live, sorted by id.
+ * key: cell id cx + G (cy + G cz) of the moved position in the last step;
+ * event: unimolecular rule fired in the last step (-1 none); partner: id of
+ * the confirmed partner in the last step (MABM_NONE none).  key, event and
+ * partner need MABM_FLAG_RECORD (else MABM_NONE / -1).  Any pointer may be
+ * NULL.  Synchronises. */
+mabm_status mabm_export(mabm_sim* sim, uint32_t capacity, uint32_t* id, uint8_t* species,
+                        float* x, float* y, float* z, uint32_t* key, int32_t* event,
+                        uint32_t* partner);
+
+/* Replace the initial placement (or resume a checkpoint): n agents with the
+ * given ids (all < next_id), species and positions (inside the volume), and
+ * the step counter t.  Finalizes the model.  Synchronises. */
+mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uint8_t* species,
+                        const float* x, const float* y, const float* z, uint32_t next_id,
+                        uint32_t t);
+
+/* Per-kernel timing with HIP events recorded on the simulation's stream:
+ * enable (1) or disable (0); read returns, per kernel of the step, the
+ * number of launches timed and their total milliseconds (synchronises).
+ * names receives a static string per kernel. */
+#define MABM_N_KERNELS 8
+mabm_status mabm_profile(mabm_sim* sim, int32_t enable);
+mabm_status mabm_profile_read(mabm_sim* sim, const char** names, uint64_t* launches,
+                              double* total_ms);
+
+/* Sum over all steps so far of the live agents at the start of each step
+ * (the agent-update count).  Synchronises. */
+mabm_status mabm_agent_updates(mabm_sim* sim, uint64_t* out);
+
+/* Free the host handle (the arena and stream stay the caller's). */
+mabm_status mabm_destroy_sim(mabm_sim* sim);
+
+/* Message of the last failing call on sim (or of the last failed create
+ * when sim is NULL).  Valid until the next call on sim. */
+const char* mabm_last_error(const mabm_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MABM_H */

@@ -1,0 +1,217 @@
+"""MI355X (gfx950) molecule-agent step engine: Python binding of libmabm.so.
+
+Argument marshalling only.  Every step of the simulation runs in the HIP
+kernels of ``csrc/``; PyTorch provides the device arena (a ``torch.uint8``
+tensor) and the stream.  If the library is not built, importing works but
+every call raises: there is no CPU fallback.
+
+The simulation is the per-timestep molecule-agent update of Maestri,
+"Towards In Silico Cancer Therapy Design" (Abstract; Sec. 2): Brownian
+motion of every molecule, proximity-based binding, product release,
+compartment crossing, emission and degradation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmabm.so")
+
+OK, E_INVALID, E_STATE, E_NOMEM, E_CAPACITY, E_DEVICE = 0, -1, -2, -3, -4, -5
+_NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_CAPACITY",
+          -5: "E_DEVICE"}
+ABI_VERSION = 1
+FLAG_RECORD = 1
+NONE32 = 0xFFFFFFFF
+N_KERNELS = 8
+
+
+class MabmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("geometry", ctypes.c_int32),
+                ("box_um", ctypes.c_float), ("outer_radius_um", ctypes.c_float),
+                ("inner_radius_um", ctypes.c_float), ("dt_s", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("capacity", ctypes.c_uint32),
+                ("cell_um", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class Rule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reactant", ctypes.c_int32 * 2),
+                ("product", ctypes.c_int32 * 2), ("radius_um", ctypes.c_float),
+                ("prob_per_step", ctypes.c_double), ("placement", ctypes.c_int32),
+                ("release_radius_um", ctypes.c_float), ("from_comp", ctypes.c_int32),
+                ("to_comp", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmabm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        c, P = ctypes, ctypes.c_void_p
+        L.mabm_arena_bytes.restype = c.c_size_t
+        L.mabm_arena_bytes.argtypes = [c.POINTER(Config), c.c_uint32, c.c_uint32]
+        L.mabm_create_sim.argtypes = [c.POINTER(Config), P, c.c_size_t, P, c.POINTER(P)]
+        L.mabm_add_species.argtypes = [P, c.c_char_p, c.c_float, c.c_uint32, c.c_int32,
+                                       c.POINTER(c.c_int32)]
+        L.mabm_add_rule.argtypes = [P, c.POINTER(Rule), c.POINTER(c.c_int32)]
+        L.mabm_grid.argtypes = [P, c.POINTER(c.c_uint32), c.POINTER(c.c_float)]
+        L.mabm_step.argtypes = [P, c.c_uint32]
+        L.mabm_counts.argtypes = [P, P, c.c_uint32, P]
+        L.mabm_size.argtypes = [P, P, P]
+        L.mabm_export.argtypes = [P, c.c_uint32, P, P, P, P, P, P, P, P]
+        L.mabm_import.argtypes = [P, c.c_uint32, P, P, P, P, P, c.c_uint32, c.c_uint32]
+        L.mabm_profile.argtypes = [P, c.c_int32]
+        L.mabm_profile_read.argtypes = [P, P, P, P]
+        L.mabm_agent_updates.argtypes = [P, P]
+        L.mabm_destroy_sim.argtypes = [P]
+        L.mabm_last_error.restype = c.c_char_p
+        L.mabm_last_error.argtypes = [P]
+        for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
+                     "mabm_step", "mabm_counts", "mabm_size", "mabm_export", "mabm_import",
+                     "mabm_profile", "mabm_profile_read", "mabm_agent_updates",
+                     "mabm_destroy_sim"):
+            getattr(L, name).restype = c.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_config(model, record: bool = False, cell_um: Optional[float] = None,
+                capacity: Optional[int] = None) -> Config:
+    return Config(ABI_VERSION, int(model.geometry), float(model.box_um),
+                  float(model.outer_radius_um), float(model.inner_radius_um), float(model.dt_s),
+                  int(model.seed), int(capacity if capacity is not None else model.capacity),
+                  float(cell_um if cell_um is not None else model.cell_um),
+                  FLAG_RECORD if record else 0)
+
+
+def arena_bytes(model, record: bool = False, cell_um: Optional[float] = None,
+                capacity: Optional[int] = None) -> int:
+    cfg = make_config(model, record, cell_um, capacity)
+    return int(lib().mabm_arena_bytes(ctypes.byref(cfg), len(model.species), len(model.rules)))
+
+
+class Sim:
+    """One simulation on the GPU.  ``model`` is a workloads.Model (species,
+    rules, geometry, dt, seed, capacity)."""
+
+    def __init__(self, model, record: bool = False, cell_um: Optional[float] = None,
+                 capacity: Optional[int] = None, stream=None, device: str = "cuda",
+                 arena=None):
+        import torch
+        L = lib()
+        self.n_species = len(model.species)
+        self.cfg = make_config(model, record, cell_um, capacity)
+        nbytes = int(L.mabm_arena_bytes(ctypes.byref(self.cfg), self.n_species,
+                                        len(model.rules)))
+        if nbytes == 0:
+            raise MabmError(E_INVALID, "invalid configuration")
+        self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                                  device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        h = ctypes.c_void_p()
+        rc = L.mabm_create_sim(ctypes.byref(self.cfg), ctypes.c_void_p(self.arena.data_ptr()),
+                               self.arena.numel(), ctypes.c_void_p(self.stream.cuda_stream),
+                               ctypes.byref(h))
+        if rc != OK:
+            raise MabmError(rc, L.mabm_last_error(None).decode())
+        self._h = h
+        out = ctypes.c_int32()
+        for sp in model.species:
+            self._chk(L.mabm_add_species(h, sp.name.encode(), float(sp.diffusion_um2_s),
+                                         int(sp.count), int(sp.compartment), ctypes.byref(out)))
+        for r in model.rules:
+            rr = Rule(int(r.kind), (ctypes.c_int32 * 2)(*r.reactants),
+                      (ctypes.c_int32 * 2)(*r.products), float(r.radius_um),
+                      float(r.prob_per_step), int(r.placement), float(r.release_radius_um),
+                      int(r.from_comp), int(r.to_comp))
+            self._chk(L.mabm_add_rule(h, ctypes.byref(rr), ctypes.byref(out)))
+
+    def _chk(self, rc: int) -> int:
+        if rc != OK:
+            raise MabmError(rc, lib().mabm_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mabm_destroy_sim(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self, n: int = 1):
+        self._chk(lib().mabm_step(self._h, int(n)))
+
+    def grid(self):
+        g = ctypes.c_uint32()
+        h = ctypes.c_float()
+        self._chk(lib().mabm_grid(self._h, ctypes.byref(g), ctypes.byref(h)))
+        return int(g.value), float(h.value)
+
+    def counts(self):
+        out = np.zeros(self.n_species, np.uint64)
+        t = np.zeros(1, np.uint64)
+        self._chk(lib().mabm_counts(self._h, _ptr(out), self.n_species, _ptr(t)))
+        return out, int(t[0])
+
+    def size(self):
+        n = np.zeros(1, np.uint32)
+        nid = np.zeros(1, np.uint32)
+        self._chk(lib().mabm_size(self._h, _ptr(n), _ptr(nid)))
+        return int(n[0]), int(nid[0])
+
+    def export(self) -> dict:
+        n, _ = self.size()
+        m = max(n, 1)
+        out = dict(id=np.zeros(m, np.uint32), species=np.zeros(m, np.uint8),
+                   x=np.zeros(m, np.float32), y=np.zeros(m, np.float32),
+                   z=np.zeros(m, np.float32), key=np.zeros(m, np.uint32),
+                   event=np.zeros(m, np.int32), partner=np.zeros(m, np.uint32))
+        self._chk(lib().mabm_export(self._h, m, *(_ptr(out[k]) for k in
+                                                 ("id", "species", "x", "y", "z", "key", "event",
+                                                  "partner"))))
+        return {k: v[:n] for k, v in out.items()}
+
+    def import_state(self, ids, species, x, y, z, next_id: int, t: int = 0):
+        ids = np.ascontiguousarray(ids, np.uint32)
+        species = np.ascontiguousarray(species, np.uint8)
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        z = np.ascontiguousarray(z, np.float32)
+        self._chk(lib().mabm_import(self._h, len(ids), _ptr(ids), _ptr(species), _ptr(x),
+                                    _ptr(y), _ptr(z), int(next_id), int(t)))
+
+    def profile(self, enable: bool = True):
+        self._chk(lib().mabm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        names = (ctypes.c_char_p * N_KERNELS)()
+        launches = np.zeros(N_KERNELS, np.uint64)
+        ms = np.zeros(N_KERNELS, np.float64)
+        self._chk(lib().mabm_profile_read(self._h, ctypes.cast(names, ctypes.c_void_p),
+                                          _ptr(launches), _ptr(ms)))
+        return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(N_KERNELS)}
+
+    def agent_updates(self) -> int:
+        out = np.zeros(1, np.uint64)
+        self._chk(lib().mabm_agent_updates(self._h, _ptr(out)))
+        return int(out[0])

@@ -1,0 +1,707 @@
+// api.hip -- host engine behind the C ABI of include/mabm.h: model
+// validation, arena carving, table construction, step sequencing on the
+// caller's stream, synchronising queries and per-kernel event timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mabm.h"
+#include "engine.hpp"
+
+using namespace mabm;
+
+namespace {
+
+struct SpeciesHost {
+    std::string name;
+    float D;
+    uint32_t count;
+    int32_t comp;
+};
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+float extent_of(const mabm_config& c)
+{
+    return c.geometry == MABM_PERIODIC_BOX ? c.box_um : c.outer_radius_um * 2.0f;
+}
+
+// cells per axis implied by the configuration alone: the requested cell
+// size, or about one cell per agent of capacity over the bounding box
+uint32_t grid_from_config(const mabm_config& c)
+{
+    const double ext = extent_of(c);
+    double g;
+    if (c.cell_um > 0.0f) g = std::floor(ext / (double)c.cell_um);
+    else g = std::round(std::cbrt((double)c.capacity));
+    return (uint32_t)std::min(1024.0, std::max(3.0, g));
+}
+
+bool config_ok(const mabm_config* c, std::string& why)
+{
+    if (!c) { why = "null config"; return false; }
+    if (c->abi_version != MABM_ABI_VERSION) { why = "abi_version mismatch"; return false; }
+    if (c->geometry < 0 || c->geometry > 2) { why = "bad geometry"; return false; }
+    if (c->geometry == MABM_PERIODIC_BOX && !(c->box_um > 0.0f)) { why = "box_um must be > 0"; return false; }
+    if (c->geometry != MABM_PERIODIC_BOX && !(c->outer_radius_um > 0.0f)) { why = "outer_radius_um must be > 0"; return false; }
+    if (c->geometry == MABM_NESTED_SPHERES &&
+        !(c->inner_radius_um > 0.0f && c->inner_radius_um < c->outer_radius_um)) {
+        why = "need 0 < inner_radius_um < outer_radius_um";
+        return false;
+    }
+    if (!(c->dt_s > 0.0f)) { why = "dt_s must be > 0"; return false; }
+    if (c->capacity == 0 || c->capacity > (1u << 30)) { why = "capacity must be in [1, 2^30]"; return false; }
+    if (c->cell_um < 0.0f) { why = "cell_um must be >= 0"; return false; }
+    return true;
+}
+
+// Arena layout: every array 256-byte aligned, in this order.
+struct Layout {
+    size_t ctl, tab, agents[2][5], key, rank, flag, event, sflag, cell_count, cell_start, tile_sum,
+        slot, prop, rkey, revent, rpartner, births, counts, total;
+    uint32_t ncells, ntiles;
+};
+
+Layout make_layout(const mabm_config& c)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t cap = c.capacity;
+    const uint32_t g = grid_from_config(c);
+    L.ncells = g * g * g;
+    L.ntiles = (L.ncells + kScanTile - 1) / kScanTile;
+    L.ctl = take(sizeof(Ctl));
+    L.tab = take(sizeof(Tables));
+    for (int b = 0; b < 2; ++b) {
+        L.agents[b][0] = take(cap * 4);
+        L.agents[b][1] = take(cap * 4);
+        L.agents[b][2] = take(cap * 4);
+        L.agents[b][3] = take(cap * 4);
+        L.agents[b][4] = take(cap);
+    }
+    L.key = take(cap * 4);
+    L.rank = take(cap * 4);
+    L.flag = take(cap);
+    L.event = take(cap);
+    L.sflag = take(cap);
+    L.cell_count = take((size_t)L.ncells * 4);
+    L.cell_start = take(((size_t)L.ncells + 1) * 4);
+    L.tile_sum = take((size_t)L.ntiles * 4);
+    L.slot = take(cap * 8);
+    L.prop = take(cap * 4);
+    L.rkey = take(cap * 4);
+    L.revent = take(cap);
+    L.rpartner = take(cap * 4);
+    L.births = take((size_t)kMaxBirthsPerStep * sizeof(Birth));
+    L.counts = take(kMaxSpecies * 8);
+    L.total = off;
+    return L;
+}
+
+uint64_t threshold_of(double p)
+{
+    if (p >= 1.0) return 1ull << 32;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+}  // namespace
+
+struct mabm_sim {
+    mabm_config cfg{};
+    hipStream_t stream = nullptr;
+    uint8_t* arena = nullptr;
+    size_t arena_bytes = 0;
+    Layout lay{};
+    Dev dev{};
+    Tables tab{};
+    std::vector<SpeciesHost> species;
+    std::vector<mabm_rule> rules;
+    bool finalized = false, failed = false, has_bimol = false;
+    int parity = 0;
+    uint32_t G = 0;
+    float h = 0.0f;
+    std::string err;
+    // per-kernel timing
+    bool prof = false;
+    std::vector<EventPair> pool;
+    std::vector<int> pending_kernel;
+    size_t pending = 0;
+    uint64_t launches[kNumKernels] = {};
+    double total_ms[kNumKernels] = {};
+};
+
+namespace {
+
+mabm_status fail(mabm_sim* s, mabm_status code, const std::string& msg)
+{
+    s->err = msg;
+    return code;
+}
+
+mabm_status hip_fail(mabm_sim* s, hipError_t e, const char* what)
+{
+    s->failed = true;
+    return fail(s, MABM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OK(sim, call)                                 \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(sim, e_, #call); \
+    } while (0)
+
+// harvest finished timing events (blocking on them)
+void harvest(mabm_sim* s)
+{
+    for (size_t k = 0; k < s->pending; ++k) {
+        EventPair& p = s->pool[k];
+        (void)hipEventSynchronize(p.b);
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            s->total_ms[s->pending_kernel[k]] += ms;
+            s->launches[s->pending_kernel[k]] += 1;
+        }
+    }
+    s->pending = 0;
+}
+
+template <class F>
+void timed(mabm_sim* s, int kid, F&& launch)
+{
+    if (!s->prof) {
+        launch();
+        return;
+    }
+    if (s->pending == s->pool.size()) harvest(s);
+    EventPair& p = s->pool[s->pending];
+    s->pending_kernel[s->pending] = kid;
+    ++s->pending;
+    (void)hipEventRecord(p.a, s->stream);
+    launch();
+    (void)hipEventRecord(p.b, s->stream);
+}
+
+mabm_status build_tables(mabm_sim* s)
+{
+    Tables& T = s->tab;
+    std::memset(&T, 0, sizeof T);
+    const mabm_config& c = s->cfg;
+    const int ns = (int)s->species.size(), nr = (int)s->rules.size();
+    if (ns == 0) return fail(s, MABM_E_INVALID, "no species");
+    T.geometry = c.geometry;
+    T.ncomp = c.geometry == MABM_NESTED_SPHERES ? 2 : 1;
+    T.ns = ns;
+    T.nr = nr;
+    T.L = c.box_um;
+    T.halfL = c.box_um * 0.5f;
+    T.Rout = c.outer_radius_um;
+    T.Rin = c.inner_radius_um;
+    T.Rout2 = (float)((double)c.outer_radius_um * (double)c.outer_radius_um);
+    T.Rin2 = (float)((double)c.inner_radius_um * (double)c.inner_radius_um);
+    T.key0 = (uint32_t)c.seed;
+    T.key1 = (uint32_t)(c.seed >> 32);
+    uint64_t acc = 0;
+    for (int k = 0; k < ns; ++k) {
+        acc += s->species[k].count;
+        T.init_end[k] = (uint32_t)acc;
+        T.init_comp[k] = s->species[k].comp;
+        T.sigma[k] = (float)std::sqrt(2.0 * (double)s->species[k].D * (double)c.dt_s);
+    }
+    if (acc > c.capacity) return fail(s, MABM_E_CAPACITY, "initial counts exceed the capacity");
+    for (int a = 0; a < kMaxSpecies; ++a)
+        for (int b = 0; b < kMaxSpecies; ++b) T.rule_of[a][b] = -1;
+    double rmax = 0.0;
+    s->has_bimol = false;
+    for (int r = 0; r < nr; ++r) {
+        const mabm_rule& u = s->rules[r];
+        RuleDev& R = T.rule[r];
+        R.kind = u.kind;
+        R.placement = u.placement;
+        R.p0 = u.product[0];
+        R.p1 = u.product[1];
+        R.to = u.to_comp;
+        R.r2 = (float)((double)u.radius_um * (double)u.radius_um);
+        R.release = u.release_radius_um;
+        R.release2 = (float)((double)u.release_radius_um * (double)u.release_radius_um);
+        R.thr = threshold_of(u.prob_per_step);
+        if (u.placement == MABM_TRANSLOCATE)
+            R.target_r = (float)(u.to_comp == 0 ? (double)c.inner_radius_um - (double)u.release_radius_um
+                                                : (double)c.inner_radius_um + (double)u.release_radius_um);
+        if (u.kind == MABM_BIMOL) {
+            T.rule_of[u.reactant[0]][u.reactant[1]] = (int8_t)r;
+            T.claimer[u.reactant[0]] = 1;
+            rmax = std::max(rmax, (double)u.radius_um);
+            s->has_bimol = true;
+        }
+        if (u.kind == MABM_UNIMOL && (u.placement == MABM_SPLIT || u.placement == MABM_EMIT))
+            T.has_births = 1;
+    }
+    // unimolecular cumulative thresholds per (species, compartment), rule-id order
+    for (int k = 0; k < ns; ++k)
+        for (int cc = 0; cc < T.ncomp; ++cc) {
+            double cum = 0.0;
+            for (int r = 0; r < nr; ++r) {
+                const mabm_rule& u = s->rules[r];
+                if (u.kind != MABM_UNIMOL || u.reactant[0] != k) continue;
+                if (u.from_comp != -1 && u.from_comp != cc) continue;
+                if (T.uni_n[k][cc] >= kMaxUni)
+                    return fail(s, MABM_E_INVALID, "more than 8 unimolecular rules for one species");
+                cum += u.prob_per_step;
+                if (cum > 1.0)
+                    return fail(s, MABM_E_INVALID,
+                                "unimolecular probabilities of a species sum above 1");
+                const int j = T.uni_n[k][cc]++;
+                T.uni_rule[k][cc][j] = (uint8_t)r;
+                T.uni_thr[k][cc][j] = threshold_of(cum);
+            }
+        }
+    // spatial hash: G cells per axis, cell size >= 1.01 R_max
+    const double ext = extent_of(c);
+    uint32_t G = grid_from_config(c);
+    if (rmax > 0.0 && ext / G < 1.01 * rmax) {
+        if (c.cell_um > 0.0f)
+            return fail(s, MABM_E_INVALID, "cell_um smaller than 1.01 x the largest contact radius");
+        G = (uint32_t)std::floor(ext / (1.01 * rmax));
+        if (G < 3) return fail(s, MABM_E_INVALID, "volume smaller than 3 cells of the contact radius");
+    }
+    s->G = G;
+    s->h = (float)(ext / G);
+    T.G = G;
+    T.lo = c.geometry == MABM_PERIODIC_BOX ? 0.0f : -c.outer_radius_um;
+    T.inv_h = (float)((double)G / ext);
+    T.stencil8 = (rmax > 0.0 && ext / G >= 2.02 * rmax) ? 1u : 0u;
+    return MABM_OK;
+}
+
+void fill_dev(mabm_sim* s)
+{
+    Dev& d = s->dev;
+    const Layout& L = s->lay;
+    uint8_t* A = s->arena;
+    d.ctl = (Ctl*)(A + L.ctl);
+    d.tab = (const Tables*)(A + L.tab);
+    for (int b = 0; b < 2; ++b) {
+        d.a[b].x = (float*)(A + L.agents[b][0]);
+        d.a[b].y = (float*)(A + L.agents[b][1]);
+        d.a[b].z = (float*)(A + L.agents[b][2]);
+        d.a[b].id = (uint32_t*)(A + L.agents[b][3]);
+        d.a[b].sp = (uint8_t*)(A + L.agents[b][4]);
+    }
+    d.key = (uint32_t*)(A + L.key);
+    d.rank = (uint32_t*)(A + L.rank);
+    d.flag = A + L.flag;
+    d.event = A + L.event;
+    d.sflag = A + L.sflag;
+    d.cell_count = (uint32_t*)(A + L.cell_count);
+    d.cell_start = (uint32_t*)(A + L.cell_start);
+    d.tile_sum = (uint32_t*)(A + L.tile_sum);
+    d.slot = (unsigned long long*)(A + L.slot);
+    d.prop = (uint32_t*)(A + L.prop);
+    d.rkey = (uint32_t*)(A + L.rkey);
+    d.revent = A + L.revent;
+    d.rpartner = (uint32_t*)(A + L.rpartner);
+    d.births = (Birth*)(A + L.births);
+    d.counts = (unsigned long long*)(A + L.counts);
+    d.capacity = s->cfg.capacity;
+}
+
+// first step / query / import: tables, hash geometry, upload, placement
+mabm_status finalize(mabm_sim* s, bool place)
+{
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    if (s->finalized) return MABM_OK;
+    mabm_status st = build_tables(s);
+    if (st != MABM_OK) return st;
+    Dev& d = s->dev;
+    d.ncells = s->G * s->G * s->G;
+    d.ntiles = (d.ncells + kScanTile - 1) / kScanTile;
+    d.n_init = place ? s->tab.init_end[s->tab.ns - 1] : 0;
+    HIP_OK(s, hipMemcpyAsync((void*)d.tab, &s->tab, sizeof(Tables), hipMemcpyHostToDevice, s->stream));
+    Ctl c{};
+    c.n_slots = d.n_init;
+    c.next_id = d.n_init;
+    HIP_OK(s, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
+    HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ncells * 4, s->stream));
+    launch_fill_records(d, s->stream);
+    if (place) launch_init(d, s->stream);
+    HIP_OK(s, hipGetLastError());
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    s->parity = 0;
+    s->finalized = true;
+    return MABM_OK;
+}
+
+mabm_status sync_ctl(mabm_sim* s, Ctl* out)
+{
+    HIP_OK(s, hipMemcpyAsync(out, s->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    if (out->err) {
+        s->failed = true;
+        if (out->err & kErrPlacement) return fail(s, MABM_E_DEVICE, "initial placement failed after 64 attempts");
+        if (out->err & kErrBirths) return fail(s, MABM_E_CAPACITY, "more than 4096 births in one step");
+        return fail(s, MABM_E_CAPACITY, "agent capacity exceeded by births");
+    }
+    return MABM_OK;
+}
+
+mabm_status live_counts(mabm_sim* s, std::vector<unsigned long long>& out, Ctl* ctl)
+{
+    launch_counts(s->dev, s->parity, s->stream);
+    HIP_OK(s, hipGetLastError());
+    out.assign(kMaxSpecies, 0ull);
+    HIP_OK(s, hipMemcpyAsync(out.data(), s->dev.counts, kMaxSpecies * 8, hipMemcpyDeviceToHost, s->stream));
+    return sync_ctl(s, ctl);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t mabm_arena_bytes(const mabm_config* cfg, uint32_t n_species, uint32_t n_rules)
+{
+    std::string why;
+    if (!config_ok(cfg, why) || n_species > MABM_MAX_SPECIES || n_rules > MABM_MAX_RULES) return 0;
+    return make_layout(*cfg).total;
+}
+
+mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t arena_bytes,
+                            void* hip_stream, mabm_sim** out)
+{
+    if (!out) return MABM_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    if (!config_ok(cfg, why)) {
+        g_create_error = why;
+        return MABM_E_INVALID;
+    }
+    Layout L = make_layout(*cfg);
+    if (!device_arena || arena_bytes < L.total) {
+        g_create_error = "arena smaller than mabm_arena_bytes()";
+        return MABM_E_NOMEM;
+    }
+    if ((uintptr_t)device_arena % 256 != 0) {
+        g_create_error = "arena must be 256-byte aligned";
+        return MABM_E_INVALID;
+    }
+    mabm_sim* s = new (std::nothrow) mabm_sim();
+    if (!s) return MABM_E_NOMEM;
+    s->cfg = *cfg;
+    s->stream = (hipStream_t)hip_stream;
+    s->arena = (uint8_t*)device_arena;
+    s->arena_bytes = arena_bytes;
+    s->lay = L;
+    fill_dev(s);
+    *out = s;
+    return MABM_OK;
+}
+
+mabm_status mabm_add_species(mabm_sim* s, const char* name, float D, uint32_t count, int32_t comp,
+                             int32_t* out_id)
+{
+    if (!s) return MABM_E_INVALID;
+    if (s->finalized || s->failed) return fail(s, MABM_E_STATE, "add_species after the model was finalized");
+    if ((int)s->species.size() >= kMaxSpecies) return fail(s, MABM_E_INVALID, "too many species");
+    const int ncomp = s->cfg.geometry == MABM_NESTED_SPHERES ? 2 : 1;
+    if (!(D >= 0.0f) || !std::isfinite(D)) return fail(s, MABM_E_INVALID, "diffusion must be finite and >= 0");
+    if (comp < 0 || comp >= ncomp) return fail(s, MABM_E_INVALID, "compartment does not exist in this geometry");
+    s->species.push_back({name ? name : "", D, count, comp});
+    if (out_id) *out_id = (int32_t)s->species.size() - 1;
+    return MABM_OK;
+}
+
+mabm_status mabm_add_rule(mabm_sim* s, const mabm_rule* r, int32_t* out_id)
+{
+    if (!s || !r) return MABM_E_INVALID;
+    if (s->finalized || s->failed) return fail(s, MABM_E_STATE, "add_rule after the model was finalized");
+    if ((int)s->rules.size() >= kMaxRules) return fail(s, MABM_E_INVALID, "too many rules");
+    const int ns = (int)s->species.size();
+    const int ncomp = s->cfg.geometry == MABM_NESTED_SPHERES ? 2 : 1;
+    auto is_sp = [&](int v) { return v >= 0 && v < ns; };
+    auto is_prod = [&](int v) { return v == -1 || is_sp(v); };
+    if (!(r->prob_per_step >= 0.0 && r->prob_per_step <= 1.0))
+        return fail(s, MABM_E_INVALID, "probability outside [0, 1]");
+    if (!is_sp(r->reactant[0]) || !is_prod(r->product[0]) || !is_prod(r->product[1]))
+        return fail(s, MABM_E_INVALID, "rule names an unknown species");
+    if (r->kind == MABM_BIMOL) {
+        if (!is_sp(r->reactant[1])) return fail(s, MABM_E_INVALID, "rule names an unknown species");
+        if (r->placement != MABM_KEEP) return fail(s, MABM_E_INVALID, "bimolecular rules use KEEP");
+        if (!(r->radius_um > 0.0f) || !std::isfinite(r->radius_um))
+            return fail(s, MABM_E_INVALID, "contact radius must be > 0");
+        for (const mabm_rule& o : s->rules)
+            if (o.kind == MABM_BIMOL &&
+                ((o.reactant[0] == r->reactant[0] && o.reactant[1] == r->reactant[1]) ||
+                 (o.reactant[0] == r->reactant[1] && o.reactant[1] == r->reactant[0])))
+                return fail(s, MABM_E_INVALID, "second bimolecular rule for one species pair");
+    } else if (r->kind == MABM_UNIMOL) {
+        if (r->reactant[1] != -1) return fail(s, MABM_E_INVALID, "unimolecular rule with two reactants");
+        if (r->from_comp < -1 || r->from_comp >= ncomp) return fail(s, MABM_E_INVALID, "bad compartment");
+        switch (r->placement) {
+        case MABM_KEEP:
+            if (r->product[1] != -1) return fail(s, MABM_E_INVALID, "KEEP has one product");
+            break;
+        case MABM_SPLIT:
+        case MABM_EMIT:
+            if (r->placement == MABM_SPLIT && r->product[0] < 0)
+                return fail(s, MABM_E_INVALID, "SPLIT needs two products");
+            if (r->product[1] < 0) return fail(s, MABM_E_INVALID, "missing emitted product");
+            if (!(r->release_radius_um >= 0.0f) || !std::isfinite(r->release_radius_um))
+                return fail(s, MABM_E_INVALID, "bad release radius");
+            break;
+        case MABM_TRANSLOCATE: {
+            if (s->cfg.geometry != MABM_NESTED_SPHERES)
+                return fail(s, MABM_E_INVALID, "translocation needs nested compartments");
+            if (r->from_comp < 0 || r->to_comp < 0 || r->to_comp >= ncomp || r->to_comp == r->from_comp)
+                return fail(s, MABM_E_INVALID, "bad translocation compartments");
+            if (r->product[1] != -1) return fail(s, MABM_E_INVALID, "TRANSLOCATE has one product");
+            const double rt = r->to_comp == 0
+                                  ? (double)s->cfg.inner_radius_um - (double)r->release_radius_um
+                                  : (double)s->cfg.inner_radius_um + (double)r->release_radius_um;
+            if (!(r->release_radius_um >= 1e-3f) || !(rt > 0.0) || !(rt < (double)s->cfg.outer_radius_um))
+                return fail(s, MABM_E_INVALID, "bad translocation offset");
+            break;
+        }
+        default:
+            return fail(s, MABM_E_INVALID, "bad placement");
+        }
+    } else {
+        return fail(s, MABM_E_INVALID, "bad rule kind");
+    }
+    s->rules.push_back(*r);
+    if (out_id) *out_id = (int32_t)s->rules.size() - 1;
+    return MABM_OK;
+}
+
+mabm_status mabm_grid(mabm_sim* s, uint32_t* g, float* h)
+{
+    if (!s) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (g) *g = s->G;
+    if (h) *h = s->h;
+    return MABM_OK;
+}
+
+mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
+{
+    if (!s) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    const Dev& d = s->dev;
+    const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
+    hipStream_t q = s->stream;
+    for (uint32_t k = 0; k < n_steps; ++k) {
+        const int cur = s->parity, nxt = cur ^ 1;
+        timed(s, kKMove, [&] { launch_move(d, cur, rec, q); });
+        timed(s, kKScanReduce, [&] { launch_scan_reduce(d, q); });
+        timed(s, kKScanTop, [&] { launch_scan_top(d, q); });
+        timed(s, kKScanDown, [&] { launch_scan_down(d, q); });
+        timed(s, kKScatter, [&] { launch_scatter(d, cur, rec, q); });
+        if (s->has_bimol) {
+            timed(s, kKPropose, [&] { launch_propose(d, nxt, q); });
+            timed(s, kKApply, [&] { launch_apply(d, nxt, rec, q); });
+        }
+        timed(s, kKBirths, [&] { launch_births(d, nxt, rec, q); });
+        s->parity = nxt;
+    }
+    HIP_OK(s, hipGetLastError());
+    return MABM_OK;
+}
+
+mabm_status mabm_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t* out_step)
+{
+    if (!s) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    std::vector<unsigned long long> c;
+    Ctl ctl{};
+    st = live_counts(s, c, &ctl);
+    if (st != MABM_OK) return st;
+    for (uint32_t k = 0; k < n_species; ++k) out[k] = k < (uint32_t)kMaxSpecies ? c[k] : 0;
+    if (out_step) *out_step = ctl.t;
+    return MABM_OK;
+}
+
+mabm_status mabm_size(mabm_sim* s, uint32_t* n_live, uint32_t* next_id)
+{
+    if (!s) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    std::vector<unsigned long long> c;
+    Ctl ctl{};
+    st = live_counts(s, c, &ctl);
+    if (st != MABM_OK) return st;
+    if (n_live) *n_live = (uint32_t)std::accumulate(c.begin(), c.end(), 0ull);
+    if (next_id) *next_id = ctl.next_id;
+    return MABM_OK;
+}
+
+mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* species, float* x,
+                        float* y, float* z, uint32_t* key, int32_t* event, uint32_t* partner)
+{
+    if (!s) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    Ctl ctl{};
+    st = sync_ctl(s, &ctl);
+    if (st != MABM_OK) return st;
+    const uint32_t n = ctl.n_slots;
+    const Agents& A = s->dev.a[s->parity];
+    std::vector<float> hx(n), hy(n), hz(n);
+    std::vector<uint32_t> hid(n), hk(n), hp(n);
+    std::vector<uint8_t> hs(n), he(n);
+    if (n) {
+        HIP_OK(s, hipMemcpyAsync(hx.data(), A.x, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hy.data(), A.y, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hz.data(), A.z, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hid.data(), A.id, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hs.data(), A.sp, n, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hk.data(), s->dev.rkey, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(he.data(), s->dev.revent, n, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hp.data(), s->dev.rpartner, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipStreamSynchronize(s->stream));
+    }
+    std::vector<uint32_t> idx;
+    idx.reserve(n);
+    for (uint32_t i = 0; i < n; ++i)
+        if (hs[i] != kDead) idx.push_back(i);
+    if (idx.size() > capacity) return fail(s, MABM_E_INVALID, "export buffer smaller than the live agents");
+    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return hid[a] < hid[b]; });
+    const bool rec = (s->cfg.flags & MABM_FLAG_RECORD) != 0;
+    for (size_t k = 0; k < idx.size(); ++k) {
+        const uint32_t i = idx[k];
+        if (id) id[k] = hid[i];
+        if (species) species[k] = hs[i];
+        if (x) x[k] = hx[i];
+        if (y) y[k] = hy[i];
+        if (z) z[k] = hz[i];
+        if (key) key[k] = rec ? hk[i] : MABM_NONE;
+        if (event) event[k] = (rec && he[i] != kNoEvent) ? (int32_t)he[i] : -1;
+        if (partner) partner[k] = rec ? hp[i] : MABM_NONE;
+    }
+    return MABM_OK;
+}
+
+mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8_t* sp,
+                        const float* x, const float* y, const float* z, uint32_t next_id, uint32_t t)
+{
+    if (!s) return MABM_E_INVALID;
+    if (s->finalized) return fail(s, MABM_E_STATE, "import after the model was finalized");
+    if (n > s->cfg.capacity) return fail(s, MABM_E_CAPACITY, "import exceeds the capacity");
+    const mabm_config& c = s->cfg;
+    const float Rout2 = (float)((double)c.outer_radius_um * (double)c.outer_radius_um);
+    const float Rin2 = (float)((double)c.inner_radius_um * (double)c.inner_radius_um);
+    (void)Rin2;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (sp[i] >= s->species.size()) return fail(s, MABM_E_INVALID, "unknown species in import");
+        if (id[i] >= next_id) return fail(s, MABM_E_INVALID, "id not below next_id");
+        if (c.geometry == MABM_PERIODIC_BOX) {
+            if (!(x[i] >= 0.0f && x[i] < c.box_um && y[i] >= 0.0f && y[i] < c.box_um && z[i] >= 0.0f &&
+                  z[i] < c.box_um))
+                return fail(s, MABM_E_INVALID, "imported position outside the box");
+        } else if (!(x[i] * x[i] + y[i] * y[i] + z[i] * z[i] <= Rout2)) {
+            return fail(s, MABM_E_INVALID, "imported position outside the volume");
+        }
+    }
+    mabm_status st = finalize(s, false);
+    if (st != MABM_OK) return st;
+    const Agents& A = s->dev.a[0];
+    if (n) {
+        HIP_OK(s, hipMemcpyAsync(A.x, x, n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(s, hipMemcpyAsync(A.y, y, n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(s, hipMemcpyAsync(A.z, z, n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(s, hipMemcpyAsync(A.id, id, n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(s, hipMemcpyAsync(A.sp, sp, n, hipMemcpyHostToDevice, s->stream));
+    }
+    Ctl ctl{};
+    ctl.t = t;
+    ctl.n_slots = n;
+    ctl.next_id = next_id;
+    HIP_OK(s, hipMemcpyAsync(s->dev.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    s->parity = 0;
+    return MABM_OK;
+}
+
+mabm_status mabm_profile(mabm_sim* s, int32_t enable)
+{
+    if (!s) return MABM_E_INVALID;
+    if (enable && s->pool.empty()) {
+        s->pool.resize(8192);
+        s->pending_kernel.resize(8192);
+        for (EventPair& p : s->pool) {
+            HIP_OK(s, hipEventCreate(&p.a));
+            HIP_OK(s, hipEventCreate(&p.b));
+        }
+    }
+    if (!enable) harvest(s);
+    s->prof = enable != 0;
+    for (int k = 0; k < kNumKernels; ++k) {
+        s->launches[k] = 0;
+        s->total_ms[k] = 0.0;
+    }
+    s->pending = 0;
+    return MABM_OK;
+}
+
+mabm_status mabm_profile_read(mabm_sim* s, const char** names, uint64_t* launches, double* total_ms)
+{
+    if (!s) return MABM_E_INVALID;
+    harvest(s);
+    for (int k = 0; k < kNumKernels; ++k) {
+        if (names) names[k] = kKernelNames[k];
+        if (launches) launches[k] = s->launches[k];
+        if (total_ms) total_ms[k] = s->total_ms[k];
+    }
+    return MABM_OK;
+}
+
+mabm_status mabm_agent_updates(mabm_sim* s, uint64_t* out)
+{
+    if (!s || !out) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    Ctl ctl{};
+    st = sync_ctl(s, &ctl);
+    if (st != MABM_OK) return st;
+    *out = ctl.agent_updates;
+    return MABM_OK;
+}
+
+mabm_status mabm_destroy_sim(mabm_sim* s)
+{
+    if (!s) return MABM_E_INVALID;
+    (void)hipStreamSynchronize(s->stream);
+    for (EventPair& p : s->pool) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    delete s;
+    return MABM_OK;
+}
+
+const char* mabm_last_error(const mabm_sim* s)
+{
+    if (!s) return g_create_error.c_str();
+    return s->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+// device_math.hpp -- counter-based random numbers, the Gaussian transform and
+// the geometry predicates of the molecule-agent step, for gfx950.
+//
+// Everything here is a pure function of its arguments and uses only IEEE
+// binary32 +, -, *, / and sqrt (the library is built with -ffp-contract=off,
+// denormals kept, correctly rounded division and square root), so every
+// result is reproducible bit for bit from the step definition.
+#pragma once
+
+#include "engine.hpp"
+
+namespace mabm {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds over a
+// 4-word counter; between rounds the 2-word key advances by the golden-ratio
+// and sqrt(3)-1 Weyl increments.  A round takes the 32x32->64 products of
+// words 0 and 2 with the two round multipliers and mixes their halves with
+// words 1 and 3 and the key.
+struct U4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
+                                     uint32_t c2, uint32_t c3)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0;
+        const uint32_t n2 = hiA ^ c3 ^ k1;
+        c0 = n0;
+        c1 = loB;
+        c2 = n2;
+        c3 = loA;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw(const Tables& T, uint32_t c0, uint32_t c1, uint32_t pur,
+                                   uint32_t c3)
+{
+    return philox(T.key0, T.key1, c0, c1, pur, c3);
+}
+
+// 24-bit uniforms on [0,1) and (0,1], exact in binary32.
+__device__ __forceinline__ float u01(uint32_t w) { return float(w >> 8) * 0x1p-24f; }
+__device__ __forceinline__ float u01_open0(uint32_t w) { return float((w >> 8) + 1u) * 0x1p-24f; }
+
+// ln x for x in (0, 1]: split x = m 2^e, fold m above sqrt 2 down by one
+// octave, then ln m = 2 atanh(s) with s = (m-1)/(m+1) and the odd series of
+// atanh through s^11 by Horner's rule; e ln 2 is added as a 16-bit head
+// (exact product) and a float tail.
+__device__ __forceinline__ float ln_unit(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    int e = int((b >> 23) & 0xFFu) - 127;
+    float m = __uint_as_float((b & 0x007FFFFFu) | 0x3F800000u);
+    if (m > 0x1.6a09e6p+0f) {  // sqrt 2 rounded to float
+        m = m * 0.5f;
+        e = e + 1;
+    }
+    const float s = (m - 1.0f) / (m + 1.0f);
+    const float s2 = s * s;
+    float h = 1.0f / 11.0f;
+    h = h * s2 + 1.0f / 9.0f;
+    h = h * s2 + 1.0f / 7.0f;
+    h = h * s2 + 1.0f / 5.0f;
+    h = h * s2 + 1.0f / 3.0f;
+    h = h * s2;
+    const float ln_m = (s + s * h) * 2.0f;
+    const float fe = float(e);
+    return fe * 0x1.62e4p-1f + (fe * 0x1.7f7d1cp-20f + ln_m);
+}
+
+// sin and cos of 2 pi a, a in [0,1) on the 2^-24 grid: exact quadrant and
+// remainder, fold of the remainder above 1/2 (swapping sin and cos), and the
+// Maclaurin series of sin (x^11) and cos (x^12) on [0, pi/4].
+__device__ __forceinline__ void sincos_turn(float a, float& sn, float& cs)
+{
+    const float a4 = a * 4.0f;
+    const int quad = int(a4);
+    float r = a4 - float(quad);
+    const bool fold = r > 0.5f;
+    if (fold) r = 1.0f - r;
+    const float x = r * 0x1.921fb6p+0f;  // pi/2 rounded to float
+    const float x2 = x * x;
+    float ps = -(1.0f / 39916800.0f);
+    ps = ps * x2 + 1.0f / 362880.0f;
+    ps = ps * x2 + -(1.0f / 5040.0f);
+    ps = ps * x2 + 1.0f / 120.0f;
+    ps = ps * x2 + -(1.0f / 6.0f);
+    ps = ps * x2;
+    const float sx = x + x * ps;
+    float pc = 1.0f / 479001600.0f;
+    pc = pc * x2 + -(1.0f / 3628800.0f);
+    pc = pc * x2 + 1.0f / 40320.0f;
+    pc = pc * x2 + -(1.0f / 720.0f);
+    pc = pc * x2 + 1.0f / 24.0f;
+    pc = pc * x2 + -0.5f;
+    pc = pc * x2;
+    const float cx = 1.0f + pc;
+    const float s1 = fold ? cx : sx;
+    const float c1 = fold ? sx : cx;
+    switch (quad & 3) {
+    case 0: sn = s1; cs = c1; break;
+    case 1: sn = c1; cs = -s1; break;
+    case 2: sn = -s1; cs = -c1; break;
+    default: sn = -c1; cs = s1; break;
+    }
+}
+
+// Three standard normals by Box-Muller from the MOVE block of (id, t).
+__device__ __forceinline__ void normals3(const Tables& T, uint32_t id, uint32_t t, float& z0,
+                                         float& z1, float& z2)
+{
+    const U4 w = draw(T, id, t, kMove, 0u);
+    float sn, cs;
+    const float r1 = __builtin_sqrtf(-2.0f * ln_unit(u01_open0(w.w0)));
+    sincos_turn(u01(w.w1), sn, cs);
+    z0 = r1 * cs;
+    z1 = r1 * sn;
+    const float r2 = __builtin_sqrtf(-2.0f * ln_unit(u01_open0(w.w2)));
+    sincos_turn(u01(w.w3), sn, cs);
+    z2 = r2 * cs;
+}
+
+__device__ __forceinline__ float sq3(float x, float y, float z) { return x * x + y * y + z * z; }
+
+// compartment: 0 = nucleus (strictly inside R_in) in the nested geometry
+__device__ __forceinline__ int compartment(const Tables& T, float x, float y, float z)
+{
+    if (T.geometry != kNested) return 0;
+    return sq3(x, y, z) < T.Rin2 ? 0 : 1;
+}
+
+__device__ __forceinline__ float wrap_box(const Tables& T, float v)
+{
+    if (v < 0.0f) v += T.L;
+    if (v >= T.L) v -= T.L;
+    return v;
+}
+
+// inside the volume and in compartment c (always true in the box)
+__device__ __forceinline__ bool admissible(const Tables& T, float x, float y, float z, int c)
+{
+    if (T.geometry == kBox) return true;
+    const float n2 = sq3(x, y, z);
+    if (n2 > T.Rout2) return false;
+    if (T.geometry == kNested && (n2 < T.Rin2 ? 0 : 1) != c) return false;
+    return true;
+}
+
+__device__ __forceinline__ uint32_t cell_coord(const Tables& T, float v)
+{
+    const float f = __builtin_floorf((v - T.lo) * T.inv_h);
+    if (!(f >= 0.0f)) return 0u;
+    if (f >= float(T.G)) return T.G - 1u;
+    return uint32_t(f);
+}
+
+__device__ __forceinline__ uint32_t cell_of(const Tables& T, float x, float y, float z)
+{
+    return cell_coord(T, x) + T.G * (cell_coord(T, y) + T.G * cell_coord(T, z));
+}
+
+}  // namespace mabm

@@ -1,0 +1,122 @@
+// engine.hpp -- internal layout shared by the kernels and the host engine of
+// libmabm (device tables, control block, arena pointers, launch entry
+// points).  Not part of the public ABI (include/mabm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mabm {
+
+constexpr int kMaxSpecies = 64;
+constexpr int kMaxRules = 255;
+constexpr int kMaxUni = 8;        // unimolecular rules per (species, compartment)
+constexpr uint8_t kDead = 0xFF;   // species byte of a consumed agent (hole)
+constexpr uint8_t kNoEvent = 0xFF;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kMaxBirthsPerStep = 4096;  // births sorted by one workgroup
+constexpr int kScanItems = 8;                 // cells per thread in the scan
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = kScanItems * kScanThreads;
+
+// Philox counter "purpose" words (third counter word).
+enum Purpose : uint32_t { kInit = 0, kUni = 1, kMove = 2, kPair = 3, kPrio = 4, kBirth = 5 };
+
+enum Geometry : int32_t { kBox = 0, kSphere = 1, kNested = 2 };
+enum Placement : int32_t { kKeep = 0, kSplit = 1, kEmit = 2, kTranslocate = 3 };
+
+// sticky device error bits
+enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u };
+
+struct RuleDev {
+    int32_t kind, placement, p0, p1, to;
+    float r2;        // squared contact radius (BIMOL)
+    float release;   // release-ball radius / translocation offset
+    float release2;  // squared release radius
+    float target_r;  // translocation landing radius
+    uint32_t pad;
+    uint64_t thr;    // Bernoulli threshold in [0, 2^32] (BIMOL)
+};
+
+struct Tables {
+    int32_t geometry, ncomp, ns, nr;
+    float L, halfL, Rout, Rout2, Rin, Rin2;
+    float lo, inv_h;
+    uint32_t G, stencil8;  // cells per axis; 1 = 8-cell stencil (h >= 2 R_max)
+    uint32_t key0, key1;   // Philox key (seed low, high)
+    uint32_t has_births, pad;
+    uint32_t init_end[kMaxSpecies];  // prefix sums of initial counts (placement)
+    int32_t init_comp[kMaxSpecies];
+    float sigma[kMaxSpecies];
+    uint8_t claimer[kMaxSpecies];
+    uint8_t uni_n[kMaxSpecies][2];
+    uint8_t uni_rule[kMaxSpecies][2][kMaxUni];
+    uint64_t uni_thr[kMaxSpecies][2][kMaxUni];
+    int8_t rule_of[kMaxSpecies][kMaxSpecies];
+    RuleDev rule[kMaxRules];
+};
+
+struct Ctl {
+    uint32_t t;         // step counter
+    uint32_t n_slots;   // entries of the current agent arrays (holes included)
+    uint32_t n_binned;  // agents binned this step
+    uint32_t n_births;  // birth records appended this step
+    uint32_t next_id;
+    uint32_t err;       // ErrBit, sticky
+    uint32_t pad[2];
+    unsigned long long agent_updates;  // sum of live agents at step starts
+};
+
+struct Birth {
+    uint32_t parent, sp;
+    float x, y, z;
+};
+
+struct Agents {
+    float *x, *y, *z;
+    uint32_t* id;
+    uint8_t* sp;
+};
+
+struct Dev {
+    Ctl* ctl;
+    const Tables* tab;
+    Agents a[2];          // ping-pong agent arrays
+    uint32_t* key;        // per pre-sort slot: cell key (kNone: not binned)
+    uint32_t* rank;       // per pre-sort slot: rank within its cell
+    uint8_t* flag;        // per pre-sort slot: 1 = busy (had an event)
+    uint8_t* event;       // per pre-sort slot: event rule (record mode)
+    uint8_t* sflag;       // per sorted agent: busy
+    uint32_t* cell_count;
+    uint32_t* cell_start;  // ncells + 1
+    uint32_t* tile_sum;
+    unsigned long long* slot;
+    uint32_t* prop;        // per sorted agent: proposed partner index
+    uint32_t* rkey;        // record arrays, indexed like the current agents
+    uint8_t* revent;
+    uint32_t* rpartner;
+    Birth* births;
+    unsigned long long* counts;  // kMaxSpecies
+    uint32_t capacity, ncells, ntiles, n_init;
+};
+
+// kernel indices for per-kernel timing
+enum KernelId { kKMove = 0, kKScanReduce, kKScanTop, kKScanDown, kKScatter, kKPropose, kKApply,
+                kKBirths, kNumKernels };
+extern const char* const kKernelNames[kNumKernels];
+
+// launch entry points (kernels.hip); each enqueues one kernel on `s`
+void launch_init(const Dev& d, hipStream_t s);
+void launch_move(const Dev& d, int cur, int record, hipStream_t s);
+void launch_scan_reduce(const Dev& d, hipStream_t s);
+void launch_scan_top(const Dev& d, hipStream_t s);
+void launch_scan_down(const Dev& d, hipStream_t s);
+void launch_scatter(const Dev& d, int cur, int record, hipStream_t s);
+void launch_propose(const Dev& d, int nxt, hipStream_t s);
+void launch_apply(const Dev& d, int nxt, int record, hipStream_t s);
+void launch_births(const Dev& d, int nxt, int record, hipStream_t s);
+void launch_counts(const Dev& d, int cur, hipStream_t s);
+void launch_fill_records(const Dev& d, hipStream_t s);
+
+}  // namespace mabm

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Positions (float32 bits), species, ids, cell ids at the library's grid,
+unimolecular events and confirmed partners are compared for every live
+agent, id-keyed, at several checkpoints; species counts and the step
+counter are compared too.  Sizes: the C1 workload at full size and horizon,
+scaled C2/C3 models that the oracle finishes in seconds while spanning many
+cells and a ragged tail, and the full 2M-agent C2 and a 1M-agent C3 for a
+few steps in the launch configuration the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import assert_same, run_pair, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14603_amd as mabm
+    mabm.lib()  # raises if the HIP library is not built
+
+
+def test_c1_small_every_step():
+    m = W.c1(n_a=1500, n_b=1500, box_um=2.0 * (3000 / 20000) ** (1 / 3), unbind_p=2e-2)
+    run_pair(m, list(range(1, 31)) + [60, 120])
+
+
+def test_c1_full_size_full_horizon():
+    run_pair(W.c1(), [1, 2, 10, 100, 250, 500, 1000])
+
+
+def test_c2_scaled():
+    run_pair(W.c2(20_000, seed=42, steps=200), [1, 5, 50, 200])
+
+
+def test_c3_scaled_births_and_translocation():
+    m = W.c3(20_000, seed=12, n_genes=300)
+    run_pair(m, [1, 10, 100, 300])
+
+
+def test_c2_full_size_in_bench_configuration():
+    # the benchmark's configuration: 2M agents, no recording, library-chosen grid
+    run_pair(W.c2(), [1, 3], record=False)
+    run_pair(W.c2(), [2], record=True)
+
+
+def test_c3_one_million_few_steps():
+    run_pair(W.c3(1_000_000, seed=314), [1, 4])
+
+
+def test_ragged_and_tiny_sizes():
+    for n in (1, 2, 3, 255, 256, 257, 1023, 4097):
+        m = W.c1(n_a=(n + 1) // 2, n_b=n // 2, box_um=0.2, unbind_p=0.05)
+        run_pair(m, [1, 7])
+
+
+def test_empty_simulation():
+    m = W.c1(n_a=0, n_b=0, box_um=1.0)
+    run_pair(m, [1, 3])
+
+
+def test_cell_size_does_not_change_results():
+    import paper_2606_14603_amd as mabm
+    m = W.c2(20_000, seed=7)
+    outs = []
+    for cell in (0.0, 0.05, 0.19):
+        g = mabm.Sim(m, record=True, cell_um=cell)
+        say(f"[cell] cell_um={cell} grid={g.grid()}")
+        g.step(40)
+        e = g.export()
+        e.pop("key")
+        outs.append(e)
+    for e in outs[1:]:
+        for k in e:
+            assert np.array_equal(e[k].view(np.uint32) if e[k].dtype == np.float32 else e[k],
+                                  outs[0][k].view(np.uint32) if e[k].dtype == np.float32
+                                  else outs[0][k]), k
+
+
+def test_two_runs_bit_identical_and_record_flag_neutral():
+    import paper_2606_14603_amd as mabm
+    m = W.c3(20_000, seed=101010, n_genes=200)
+    res = []
+    for rec in (True, True, False):
+        g = mabm.Sim(m, record=rec)
+        g.step(120)
+        e = g.export()
+        for f in ("key", "event", "partner"):
+            e.pop(f)
+        res.append(e)
+    for e in res[1:]:
+        for k in e:
+            a, b = e[k], res[0][k]
+            if a.dtype == np.float32:
+                a, b = a.view(np.uint32), b.view(np.uint32)
+            assert np.array_equal(a, b), k
+
+
+def _import_pair(agents, next_id, t=0):
+    def imp(sim):
+        sim.import_state([a[0] for a in agents], [a[1] for a in agents],
+                         [a[2] for a in agents], [a[3] for a in agents],
+                         [a[4] for a in agents], next_id, t)
+    imp.t0 = t
+    return imp
+
+
+def test_engineered_contacts_match_oracle():
+    R = 2.0 ** -7
+    A, B, C = 0, 1, 2
+    m = W.Model("claims", W.PERIODIC_BOX, 1e-6, 0,
+                [W.Species("A", 0.0, 0), W.Species("B", 0.0, 0), W.Species("C", 0.0, 0)],
+                [W.bimol(A, B, C, -1, R, 1.0)], box_um=1.0, capacity=64)
+    h = 0.5
+    agents = [(10, A, h, h, h), (3, B, h, h - R, h), (5, B, h + R, h, h),
+              (11, A, 0.25, 0.25, 0.25), (20, B, 0.25 + R + 2.0 ** -10, 0.25, 0.25),
+              (12, A, 2.0 ** -10, 0.75, 0.75), (21, B, 1.0 - 2.0 ** -8, 0.75, 0.75),
+              (30, B, h, 0.25, 0.75), (31, A, h - 2.0 ** -8, 0.25, 0.75),
+              (32, A, h + 2.0 ** -8, 0.25, 0.75),
+              (33, B, h + 2.0 ** -8 + 2.0 ** -8 + 2.0 ** -9, 0.25, 0.75)]
+    run_pair(m, [1, 2], importer=_import_pair(agents, 64))
+    sp = [W.Species(n, 0.0, 0) for n in ("A", "P", "D", "X", "E", "S", "Q")]
+    rules = [W.bimol(0, 0, 1, 2, R, 1.0), W.bimol(0, 3, 1, 3, R, 1.0), W.unimol(3, 3, 1.0),
+             W.bimol(4, 5, 4, 6, R, 1.0)]
+    m2 = W.Model("homo", W.PERIODIC_BOX, 1e-6, 7, sp, rules, box_um=1.0, capacity=64)
+    agents2 = [(9, 0, 0.5, 0.5, 0.5), (4, 0, 0.5 + 2.0 ** -8, 0.5, 0.5),
+               (6, 0, 0.25, 0.25, 0.25), (7, 3, 0.25 + 2.0 ** -8, 0.25, 0.25),
+               (1, 4, 0.75, 0.75, 0.75), (2, 5, 0.75, 0.75 + 2.0 ** -8, 0.75)]
+    run_pair(m2, [1], importer=_import_pair(agents2, 16, t=9))
+
+
+def test_dense_random_contacts_match_oracle():
+    rng = np.random.default_rng(3)
+    n, L = 3000, 0.25
+    m = W.Model("dense", W.PERIODIC_BOX, 1e-6, 11,
+                [W.Species("A", 0.5, 0), W.Species("B", 0.5, 0), W.Species("C", 0.2, 0),
+                 W.Species("D", 0.2, 0)],
+                [W.bimol(0, 1, 2, 3, 0.02, 0.7), W.bimol(0, 0, 2, 2, 0.015, 0.5),
+                 W.unimol(2, 0, 0.05, placement=W.SPLIT, p2=1, release=0.01),
+                 W.unimol(3, 1, 0.05)],
+                box_um=L, capacity=2 * n)
+    pos = rng.uniform(0, L, (n, 3)).astype(np.float32)
+    agents = [(int(i), int(s), float(p[0]), float(p[1]), float(p[2]))
+              for i, s, p in zip(rng.permutation(5 * n)[:n], rng.integers(0, 2, n), pos)]
+    run_pair(m, [1, 2, 5, 20], importer=_import_pair(agents, 5 * n, t=3))
+
+
+def test_nested_dense_membrane_contacts():
+    rng = np.random.default_rng(4)
+    n = 4000
+    m = W.Model("memb", W.NESTED_SPHERES, 1e-6, 5,
+                [W.Species("A", 1.0, 0), W.Species("B", 1.0, 0), W.Species("C", 0.5, 0)],
+                [W.bimol(0, 1, 2, -1, 0.02, 0.8),
+                 W.unimol(2, 0, 0.02, placement=W.SPLIT, p2=1, release=0.01),
+                 W.unimol(0, -1, 0.01, placement=W.TRANSLOCATE, release=0.005, from_comp=0,
+                          to_comp=1),
+                 W.unimol(1, -1, 0.01, placement=W.TRANSLOCATE, release=0.005, from_comp=1,
+                          to_comp=0)],
+                outer_radius_um=0.5, inner_radius_um=0.3, capacity=2 * n)
+    # a shell of agents hugging the membrane on both sides
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    r = 0.3 + rng.uniform(-0.02, 0.02, n)
+    p = (d * r[:, None]).astype(np.float32)
+    agents = [(i, int(s), float(q[0]), float(q[1]), float(q[2]))
+              for i, (s, q) in enumerate(zip(rng.integers(0, 2, n), p))]
+    run_pair(m, [1, 2, 10, 40], importer=_import_pair(agents, n))
