@@ -68,6 +68,8 @@ def lib() -> ctypes.CDLL:
         L.orc_log.argtypes = [c.c_float]
         L.orc_sincos2pi.argtypes = [c.c_float, P, P]
         L.orc_gauss3.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, P]
+        L.orc_event_word.restype = c.c_uint32
+        L.orc_event_word.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32]
         _lib = L
     return _lib
 
@@ -177,6 +179,10 @@ def sincos2pi(a: float):
     c = np.zeros(1, np.float32)
     lib().orc_sincos2pi(float(a), _ptr(s), _ptr(c))
     return float(s[0]), float(c[0])
+
+
+def event_word(seed: int, agent_id: int, t: int) -> int:
+    return int(lib().orc_event_word(int(seed), int(agent_id), int(t)))
 
 
 def gauss3(seed: int, agent_id: int, t: int) -> np.ndarray:

@@ -34,7 +34,8 @@
 #define NONE32 0xFFFFFFFFu
 
 /* Philox counter "purpose" words (third counter word). */
-enum { PUR_INIT = 0, PUR_UNI = 1, PUR_MOVE = 2, PUR_PAIR = 3, PUR_PRIO = 4, PUR_BIRTH = 5 };
+/* (word 1 is not used: the event draw shares the MOVE block, see O2) */
+enum { PUR_INIT = 0, PUR_MOVE = 2, PUR_PAIR = 3, PUR_PRIO = 4, PUR_BIRTH = 5 };
 
 typedef struct {
     int kind, r0, r1, p0, p1, placement, from, to;
@@ -232,11 +233,22 @@ void orc_sincos2pi(float a, float* out_s, float* out_c)
     }
 }
 
-/* O3: three N(0,1) draws by Box-Muller from one Philox block (id, t, MOVE). */
-static void gauss3(const uint32_t key[2], uint32_t id, uint32_t t, float z[3])
+/* O2/O3: the Philox block (id, t, MOVE) of one agent and step.  Its four
+ * high 24-bit fields feed Box-Muller; its four low bytes, word 0 lowest,
+ * form the 32-bit event draw. */
+static void move_block(const uint32_t key[2], uint32_t id, uint32_t t, uint32_t w[4])
 {
-    uint32_t w[4];
     draw_k(key, id, t, PUR_MOVE, 0, w);
+}
+
+static uint32_t event_word(const uint32_t w[4])
+{
+    return (w[0] & 0xFFu) | ((w[1] & 0xFFu) << 8) | ((w[2] & 0xFFu) << 16) | ((w[3] & 0xFFu) << 24);
+}
+
+/* O3: three N(0,1) draws by Box-Muller from the MOVE block. */
+static void gauss3_w(const uint32_t w[4], float z[3])
+{
     float r1 = sqrtf(-2.0f * orc_log(unif_plus(w[0])));
     float sn, cs;
     orc_sincos2pi(unif(w[1]), &sn, &cs);
@@ -249,8 +261,16 @@ static void gauss3(const uint32_t key[2], uint32_t id, uint32_t t, float z[3])
 
 void orc_gauss3(uint64_t seed, uint32_t id, uint32_t t, float out[3])
 {
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    gauss3(key, id, t, out);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, w[4];
+    move_block(key, id, t, w);
+    gauss3_w(w, out);
+}
+
+uint32_t orc_event_word(uint64_t seed, uint32_t id, uint32_t t)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)}, w[4];
+    move_block(key, id, t, w);
+    return event_word(w);
 }
 
 /* ------------------------------------------------------------------------
@@ -661,18 +681,18 @@ static void phase_move(orc_sim* s, uint32_t i)
     float x = s->x[i], y = s->y[i], z = s->z[i];
     int c0 = comp_of(s, x, y, z);
 
+    uint32_t w[4];
+    move_block(s->pkey, id, t, w);
+
     /* O2: one draw decides the unimolecular event (cumulative thresholds) */
     int ev = -1;
-    if (s->uni_n[sp][c0]) {
-        uint32_t w[4];
-        draw(s, id, t, PUR_UNI, 0, w);
-        for (int j = 0; j < s->uni_n[sp][c0]; ++j)
-            if ((uint64_t)w[0] < s->uni_thr[sp][c0][j]) { ev = s->uni_rule[sp][c0][j]; break; }
-    }
+    uint32_t wu = event_word(w);
+    for (int j = 0; j < s->uni_n[sp][c0]; ++j)
+        if ((uint64_t)wu < s->uni_thr[sp][c0][j]) { ev = s->uni_rule[sp][c0][j]; break; }
 
     /* O3: Brownian move */
     float g[3];
-    gauss3(s->pkey, id, t, g);
+    gauss3_w(w, g);
     float sg = s->sigma[sp];
     float x1 = x + sg * g[0], y1 = y + sg * g[1], z1 = z + sg * g[2];
 

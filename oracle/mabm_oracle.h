@@ -79,8 +79,8 @@ float orc_log(float x);
 void  orc_sincos2pi(float a, float* s, float* c);
 /* the three N(0,1) draws of the Brownian move of agent id at step t */
 void  orc_gauss3(uint64_t seed, uint32_t id, uint32_t t, float out[3]);
-/* candidate set of the propose phase for agent index i of the last step
- * (debug/pin helper): not exported. */
+/* the 32-bit unimolecular event draw of agent id at step t */
+uint32_t orc_event_word(uint64_t seed, uint32_t id, uint32_t t);
 
 #ifdef __cplusplus
 }

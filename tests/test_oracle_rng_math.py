@@ -116,3 +116,19 @@ def test_gauss3_is_standard_normal():
     assert np.all(np.abs(c[np.triu_indices(3, 1)]) < 4.0 / math.sqrt(len(z)))
     bound = math.sqrt(-2.0 * math.log(2.0**-24))
     assert np.abs(z).max() <= bound * (1 + 1e-6)
+
+
+def test_event_word_uniform_and_independent_of_the_move():
+    """The event draw takes the four low bytes of the Brownian block: it must
+    be uniform on 32 bits and uncorrelated with the three normals."""
+    seeds = (12, 42, 314, 101010)
+    w = np.array([oracle.event_word(s, i, 3) for s in seeds for i in range(30000)], np.float64)
+    z = np.array([oracle.gauss3(s, i, 3) for s in seeds for i in range(30000)], np.float64)
+    u = w / 2.0**32
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    lim = 4.0 / math.sqrt(len(u))
+    for col in range(3):
+        assert abs(np.corrcoef(u, z[:, col])[0, 1]) < lim
+        assert abs(np.corrcoef(u, np.abs(z[:, col]))[0, 1]) < lim
+    # low threshold region (first-order rates ~1e-5 .. 1e-2) is hit at its rate
+    assert abs((u < 0.01).mean() - 0.01) < 4 * math.sqrt(0.01 * 0.99 / len(u))
