@@ -24,21 +24,22 @@ sys.path.insert(0, ROOT)
 METRIC = "agent-updates/s at 2M agents; batched sweep sims/s vs serial; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
-# Algorithmic bytes per launch of each step kernel, as bytes per live agent
-# (a) and per cell of the spatial hash (c): what the kernel must read or
-# write at least once for its function.
+# Algorithmic bytes per launch of each step kernel: bytes per live agent (a),
+# per claimer (q) and per cell of the spatial hash (c) that the kernel must
+# read or write at least once for its function.
 #   move:    reads x, y, z, id, species (17 B); writes x, y, z, species (13),
-#            cell key (4), in-cell rank (4), busy flag (1)           = 39 B
-#   scatter: reads key, rank, 17 B state, flag, cell start (30); writes
-#            17 B state, flag, claim slot (26)                       = 56 B
-#   propose: reads species + flag (2), writes proposal (4); claimers' own
-#            positions and cell starts are a small extra             = 6 B
-#   apply:   reads the proposal                                      = 4 B
-#   scan_reduce: 4 B per cell; scan_down: 12 B per cell (read, start, clear)
-KERNEL_BYTES = {
-    "move": (39, 0), "scatter": (56, 0), "propose": (6, 0), "apply": (4, 0),
-    "scan_reduce": (0, 4), "scan_down": (0, 12), "scan_top": (0, 0), "births": (0, 0),
-}
+#            cell key (4), in-cell rank (4), busy flag (1)            = 39 B/agent
+#   scan_reduce: reads the count                                     =  4 B/cell
+#   scan_down:   reads the count, writes the start, clears the count =  12 B/cell
+#   scatter: reads key, rank, 17 B state, flag, cell start (30); writes 17 B
+#            state, flag, claim slot (26)                              = 56 B/agent
+#   propose: flags of the chunk (1 B/agent); per claimer its position,
+#            species and id (17) and its proposal (4)               = 1 B/agent + 21 B/claimer
+#   finish:  flags of the chunk (1 B/agent); per claimer its proposal (4)
+#                                                                   = 1 B/agent + 4 B/claimer
+KERNEL_BYTES = {"move": (39, 0, 0), "scan_reduce": (0, 0, 4), "scan_down": (0, 0, 12),
+                "scatter": (56, 0, 0), "propose": (1, 21, 0), "finish": (1, 4, 0),
+                "close": (0, 0, 0)}
 
 
 def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:
@@ -64,7 +65,8 @@ def main() -> int:
     ap.add_argument("--agents", type=int, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
-                    help="time without per-kernel events (no roofline)")
+                    help="skip the per-kernel timing region (no roofline)")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -77,38 +79,44 @@ def main() -> int:
 
     model = W.c2(args.agents)
     torch.cuda.set_device(0)
-    sim = mabm.Sim(model)
+    sim = mabm.Sim(model, graphs=not args.no_graph)
     G, h = sim.grid()
-    sim.step(args.warmup)
-    sim.counts()  # sync; surfaces any device error
-    u0 = sim.agent_updates()
-    if not args.no_profile:
-        sim.profile(True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stream = sim.stream
-    ev0.record(stream)
-    sim.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    prof = sim.profile_read() if not args.no_profile else {}
-    u1 = sim.agent_updates()
-    counts, t = sim.counts()
-    updates = u1 - u0
+    sim.step(args.warmup)
+    sim.counts()  # synchronises; surfaces any device error
+
+    def timed(steps: int):
+        u0 = sim.agent_updates()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sim.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1), sim.agent_updates() - u0
+
+    # timed region: the step as users run it (graph replay on the stream)
+    ms, updates = timed(args.steps)
     value = updates / (ms / 1e3)
     live = updates / args.steps
-    ncells = G ** 3
+    counts, t = sim.counts()
+    claimers = int(counts[[0, 3, 6]].sum())  # kinase1, p-kinase2, phosphatase claim
 
-    roof = None
-    kernels = {}
-    if prof:
+    # same number of steps with HIP events around every kernel (direct
+    # launches: events cannot sit between graph nodes) for the roofline
+    roof, kernels, ms_direct = None, {}, None
+    if not args.no_profile:
+        sim.profile(True)
+        ms_direct, _ = timed(args.steps)
+        prof = sim.profile_read()
+        sim.profile(False)
         for name, (launches, tot) in prof.items():
             if launches:
-                kernels[name] = {"launches": launches, "avg_us": 1e3 * tot / launches}
+                kernels[name] = {"launches": launches, "avg_us": round(1e3 * tot / launches, 3)}
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-        a, c = KERNEL_BYTES[dom]
-        alg = a * live + c * ncells
+        a, q, c = KERNEL_BYTES[dom]
+        alg = a * live + q * claimers + c * G ** 3
         achieved = alg / (kernels[dom]["avg_us"] * 1e-6) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -121,8 +129,10 @@ def main() -> int:
         "config": {"workload": f"c2_mapk: {model.n_agents} agents, 8 species, 12 rules, "
                                f"reflecting sphere R={model.outer_radius_um:.3f} um, dt=1 us",
                    "agents": model.n_agents, "grid": G, "cell_um": round(h, 5),
-                   "final_step": t, "live_agents_end": int(counts.sum())},
+                   "graphs": not args.no_graph, "final_step": t,
+                   "live_agents_end": int(counts.sum())},
         "roofline": roof, "kernels": kernels,
+        "ms_per_step_kernel_timed": None if ms_direct is None else ms_direct / args.steps,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model)

@@ -90,6 +90,10 @@ typedef struct {
  * of the last step, so that mabm_export can return them.  Costs extra
  * traffic; results are identical with and without it. */
 #define MABM_FLAG_RECORD 1u
+/* Launch each step's kernels directly instead of replaying a captured HIP
+ * graph (graphs are used only on a non-null stream and without per-kernel
+ * timing).  Results are identical either way. */
+#define MABM_FLAG_NO_GRAPH 2u
 
 /* Per-step rule (Sec. 2: "reactions it participates in, including
  * interacting partners, rates, and resulting products").  Species are ids
@@ -177,7 +181,7 @@ mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uin
  * enable (1) or disable (0); read returns, per kernel of the step, the
  * number of launches timed and their total milliseconds (synchronises).
  * names receives a static string per kernel. */
-#define MABM_N_KERNELS 8
+#define MABM_N_KERNELS 7
 mabm_status mabm_profile(mabm_sim* sim, int32_t enable);
 mabm_status mabm_profile_read(mabm_sim* sim, const char** names, uint64_t* launches,
                               double* total_ms);

@@ -26,8 +26,9 @@ _NAMES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_CAPACIT
           -5: "E_DEVICE"}
 ABI_VERSION = 1
 FLAG_RECORD = 1
+FLAG_NO_GRAPH = 2
 NONE32 = 0xFFFFFFFF
-N_KERNELS = 8
+N_KERNELS = 7
 
 
 class MabmError(RuntimeError):
@@ -95,12 +96,12 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 def make_config(model, record: bool = False, cell_um: Optional[float] = None,
-                capacity: Optional[int] = None) -> Config:
+                capacity: Optional[int] = None, graphs: bool = True) -> Config:
+    flags = (FLAG_RECORD if record else 0) | (0 if graphs else FLAG_NO_GRAPH)
     return Config(ABI_VERSION, int(model.geometry), float(model.box_um),
                   float(model.outer_radius_um), float(model.inner_radius_um), float(model.dt_s),
                   int(model.seed), int(capacity if capacity is not None else model.capacity),
-                  float(cell_um if cell_um is not None else model.cell_um),
-                  FLAG_RECORD if record else 0)
+                  float(cell_um if cell_um is not None else model.cell_um), flags)
 
 
 def arena_bytes(model, record: bool = False, cell_um: Optional[float] = None,
@@ -111,22 +112,26 @@ def arena_bytes(model, record: bool = False, cell_um: Optional[float] = None,
 
 class Sim:
     """One simulation on the GPU.  ``model`` is a workloads.Model (species,
-    rules, geometry, dt, seed, capacity)."""
+    rules, geometry, dt, seed, capacity).  By default the simulation gets its
+    own HIP stream, on which steps replay a captured graph."""
 
     def __init__(self, model, record: bool = False, cell_um: Optional[float] = None,
                  capacity: Optional[int] = None, stream=None, device: str = "cuda",
-                 arena=None):
+                 arena=None, graphs: bool = True):
         import torch
         L = lib()
         self.n_species = len(model.species)
-        self.cfg = make_config(model, record, cell_um, capacity)
+        self.cfg = make_config(model, record, cell_um, capacity, graphs)
         nbytes = int(L.mabm_arena_bytes(ctypes.byref(self.cfg), self.n_species,
                                         len(model.rules)))
         if nbytes == 0:
             raise MabmError(E_INVALID, "invalid configuration")
         self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8,
                                                                   device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.arena.device)
+            stream.wait_stream(torch.cuda.current_stream(self.arena.device))
+        self.stream = stream
         h = ctypes.c_void_p()
         rc = L.mabm_create_sim(ctypes.byref(self.cfg), ctypes.c_void_p(self.arena.data_ptr()),
                                self.arena.numel(), ctypes.c_void_p(self.stream.cuda_stream),
@@ -209,7 +214,8 @@ class Sim:
         ms = np.zeros(N_KERNELS, np.float64)
         self._chk(lib().mabm_profile_read(self._h, ctypes.cast(names, ctypes.c_void_p),
                                           _ptr(launches), _ptr(ms)))
-        return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(N_KERNELS)}
+        return {(names[k] or b"kernel%d" % k).decode(): (int(launches[k]), float(ms[k]))
+                for k in range(N_KERNELS)}
 
     def agent_updates(self) -> int:
         out = np.zeros(1, np.uint64)

@@ -67,8 +67,8 @@ bool config_ok(const mabm_config* c, std::string& why)
 
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
-    size_t ctl, tab, agents[2][5], key, rank, flag, event, sflag, cell_count, cell_start, tile_sum,
-        slot, prop, rkey, revent, rpartner, births, counts, total;
+    size_t ctl, tab, agents[2][5], key, rank, flag, event, sflag, cell_count, cell_start,
+        tile_sum, slot, prop, rkey, revent, rpartner, births, counts, total;
     uint32_t ncells, ntiles;
 };
 
@@ -99,8 +99,9 @@ Layout make_layout(const mabm_config& c)
     L.flag = take(cap);
     L.event = take(cap);
     L.sflag = take(cap);
-    L.cell_count = take((size_t)L.ncells * 4);
-    L.cell_start = take(((size_t)L.ncells + 1) * 4);
+    const size_t padded = (size_t)L.ntiles * kScanTile;  // whole scan tiles
+    L.cell_count = take(padded * 4);
+    L.cell_start = take((padded + 1) * 4);
     L.tile_sum = take((size_t)L.ntiles * 4);
     L.slot = take(cap * 8);
     L.prop = take(cap * 4);
@@ -132,6 +133,7 @@ struct mabm_sim {
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // one captured step per parity
     int parity = 0;
     uint32_t G = 0;
     float h = 0.0f;
@@ -335,8 +337,10 @@ mabm_status finalize(mabm_sim* s, bool place)
     Ctl c{};
     c.n_slots = d.n_init;
     c.next_id = d.n_init;
+    c.live = d.n_init;
     HIP_OK(s, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
-    HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ncells * 4, s->stream));
+    // cell counts start at zero
+    HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ntiles * kScanTile * 4, s->stream));
     launch_fill_records(d, s->stream);
     if (place) launch_init(d, s->stream);
     HIP_OK(s, hipGetLastError());
@@ -497,27 +501,63 @@ mabm_status mabm_grid(mabm_sim* s, uint32_t* g, float* h)
     return MABM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// one step: move, scan (2), scatter, [propose, finish], close
+void enqueue_step(mabm_sim* s, int cur)
+{
+    const Dev& d = s->dev;
+    const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
+    const int nxt = cur ^ 1;
+    hipStream_t q = s->stream;
+    timed(s, kKMove, [&] { launch_move(d, cur, rec, q); });
+    timed(s, kKScanReduce, [&] { launch_scan_reduce(d, q); });
+    timed(s, kKScanDown, [&] { launch_scan_down(d, q); });
+    timed(s, kKScatter, [&] { launch_scatter(d, cur, rec, q); });
+    if (s->has_bimol) timed(s, kKPropose, [&] { launch_propose(d, nxt, q); });
+    if (s->has_bimol) timed(s, kKFinish, [&] { launch_finish(d, nxt, rec, q); });
+    timed(s, kKClose, [&] { launch_close(d, nxt, rec, q); });
+}
+
+// capture one step of each parity as a graph on the caller's stream
+mabm_status capture(mabm_sim* s, int cur)
+{
+    hipGraph_t g = nullptr;
+    HIP_OK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_step(s, cur);
+    HIP_OK(s, hipStreamEndCapture(s->stream, &g));
+    const hipError_t e = hipGraphInstantiate(&s->graph[cur], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
+    return MABM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
 {
     if (!s) return MABM_E_INVALID;
     mabm_status st = finalize(s, true);
     if (st != MABM_OK) return st;
-    const Dev& d = s->dev;
-    const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
-    hipStream_t q = s->stream;
+    // graphs need a capturable (non-null) stream; per-kernel timing records
+    // events between the kernels, so it launches them directly
+    const bool graphs = s->stream != nullptr && !s->prof && !(s->cfg.flags & MABM_FLAG_NO_GRAPH);
     for (uint32_t k = 0; k < n_steps; ++k) {
-        const int cur = s->parity, nxt = cur ^ 1;
-        timed(s, kKMove, [&] { launch_move(d, cur, rec, q); });
-        timed(s, kKScanReduce, [&] { launch_scan_reduce(d, q); });
-        timed(s, kKScanTop, [&] { launch_scan_top(d, q); });
-        timed(s, kKScanDown, [&] { launch_scan_down(d, q); });
-        timed(s, kKScatter, [&] { launch_scatter(d, cur, rec, q); });
-        if (s->has_bimol) {
-            timed(s, kKPropose, [&] { launch_propose(d, nxt, q); });
-            timed(s, kKApply, [&] { launch_apply(d, nxt, rec, q); });
+        const int cur = s->parity;
+        if (graphs) {
+            if (!s->graph[cur]) {
+                st = capture(s, cur);
+                if (st != MABM_OK) return st;
+            }
+            HIP_OK(s, hipGraphLaunch(s->graph[cur], s->stream));
+        } else {
+            enqueue_step(s, cur);
         }
-        timed(s, kKBirths, [&] { launch_births(d, nxt, rec, q); });
-        s->parity = nxt;
+        s->parity = cur ^ 1;
     }
     HIP_OK(s, hipGetLastError());
     return MABM_OK;
@@ -635,6 +675,7 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
     ctl.t = t;
     ctl.n_slots = n;
     ctl.next_id = next_id;
+    ctl.live = n;
     HIP_OK(s, hipMemcpyAsync(s->dev.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;
@@ -690,6 +731,8 @@ mabm_status mabm_destroy_sim(mabm_sim* s)
 {
     if (!s) return MABM_E_INVALID;
     (void)hipStreamSynchronize(s->stream);
+    for (hipGraphExec_t& g : s->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     for (EventPair& p : s->pool) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

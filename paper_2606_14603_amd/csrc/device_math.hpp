@@ -27,14 +27,15 @@ __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
-        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
-        const uint32_t n0 = hiB ^ c1 ^ k0;
-        const uint32_t n2 = hiA ^ c3 ^ k1;
+        // one 32x32->64 multiply-add per product gives both halves
+        const uint64_t pa = uint64_t(kMulA) * c0;
+        const uint64_t pb = uint64_t(kMulB) * c2;
+        const uint32_t n0 = uint32_t(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = uint32_t(pa >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = loB;
+        c1 = uint32_t(pb);
         c2 = n2;
-        c3 = loA;
+        c3 = uint32_t(pa);
         k0 += kWeylA;
         k1 += kWeylB;
     }
@@ -114,11 +115,16 @@ __device__ __forceinline__ void sincos_turn(float a, float& sn, float& cs)
     }
 }
 
-// Three standard normals by Box-Muller from the MOVE block of (id, t).
-__device__ __forceinline__ void normals3(const Tables& T, uint32_t id, uint32_t t, float& z0,
-                                         float& z1, float& z2)
+// The 32-bit event draw: the four low bytes of the MOVE block, word 0
+// lowest (Box-Muller reads only the high 24 bits of each word).
+__device__ __forceinline__ uint32_t event_bits(const U4& w)
 {
-    const U4 w = draw(T, id, t, kMove, 0u);
+    return (w.w0 & 0xFFu) | ((w.w1 & 0xFFu) << 8) | ((w.w2 & 0xFFu) << 16) | ((w.w3 & 0xFFu) << 24);
+}
+
+// Three standard normals by Box-Muller from the MOVE block.
+__device__ __forceinline__ void normals3(const U4& w, float& z0, float& z1, float& z2)
+{
     float sn, cs;
     const float r1 = __builtin_sqrtf(-2.0f * ln_unit(u01_open0(w.w0)));
     sincos_turn(u01(w.w1), sn, cs);

@@ -14,14 +14,17 @@ constexpr int kMaxRules = 255;
 constexpr int kMaxUni = 8;        // unimolecular rules per (species, compartment)
 constexpr uint8_t kDead = 0xFF;   // species byte of a consumed agent (hole)
 constexpr uint8_t kNoEvent = 0xFF;
+constexpr uint8_t kBusyBit = 1;     // sorted flag: had a unimolecular event
+constexpr uint8_t kClaimerBit = 2;  // sorted flag: on this step's claimer list
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxBirthsPerStep = 4096;  // births sorted by one workgroup
 constexpr int kScanItems = 8;                 // cells per thread in the scan
 constexpr int kScanThreads = 256;
 constexpr int kScanTile = kScanItems * kScanThreads;
 
-// Philox counter "purpose" words (third counter word).
-enum Purpose : uint32_t { kInit = 0, kUni = 1, kMove = 2, kPair = 3, kPrio = 4, kBirth = 5 };
+// Philox counter "purpose" words (third counter word; 1 is unused: the
+// event draw shares the MOVE block).
+enum Purpose : uint32_t { kInit = 0, kMove = 2, kPair = 3, kPrio = 4, kBirth = 5 };
 
 enum Geometry : int32_t { kBox = 0, kSphere = 1, kNested = 2 };
 enum Placement : int32_t { kKeep = 0, kSplit = 1, kEmit = 2, kTranslocate = 3 };
@@ -58,13 +61,15 @@ struct Tables {
 };
 
 struct Ctl {
-    uint32_t t;         // step counter
-    uint32_t n_slots;   // entries of the current agent arrays (holes included)
-    uint32_t n_binned;  // agents binned this step
-    uint32_t n_births;  // birth records appended this step
+    uint32_t t;            // step counter
+    uint32_t n_slots;      // entries of the current agent arrays (holes included)
+    uint32_t n_binned;     // agents binned this step
+    uint32_t n_births;     // birth records appended this step
     uint32_t next_id;
-    uint32_t err;       // ErrBit, sticky
-    uint32_t pad[2];
+    uint32_t err;          // ErrBit, sticky
+    uint32_t live;         // live agents in the current arrays
+    uint32_t holes;        // agents consumed by pair rules this step
+    uint32_t pad[4];
     unsigned long long agent_updates;  // sum of live agents at step starts
 };
 
@@ -87,10 +92,10 @@ struct Dev {
     uint32_t* rank;       // per pre-sort slot: rank within its cell
     uint8_t* flag;        // per pre-sort slot: 1 = busy (had an event)
     uint8_t* event;       // per pre-sort slot: event rule (record mode)
-    uint8_t* sflag;       // per sorted agent: busy
-    uint32_t* cell_count;
-    uint32_t* cell_start;  // ncells + 1
-    uint32_t* tile_sum;
+    uint8_t* sflag;       // per sorted agent: kBusyBit | kClaimerBit
+    uint32_t* cell_count;  // ncells rounded up to whole scan tiles
+    uint32_t* cell_start;  // padded ncells + 1
+    uint32_t* tile_sum;    // per scan tile
     unsigned long long* slot;
     uint32_t* prop;        // per sorted agent: proposed partner index
     uint32_t* rkey;        // record arrays, indexed like the current agents
@@ -102,20 +107,19 @@ struct Dev {
 };
 
 // kernel indices for per-kernel timing
-enum KernelId { kKMove = 0, kKScanReduce, kKScanTop, kKScanDown, kKScatter, kKPropose, kKApply,
-                kKBirths, kNumKernels };
+enum KernelId { kKMove = 0, kKScanReduce, kKScanDown, kKScatter, kKPropose, kKFinish, kKClose,
+                kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 // launch entry points (kernels.hip); each enqueues one kernel on `s`
 void launch_init(const Dev& d, hipStream_t s);
 void launch_move(const Dev& d, int cur, int record, hipStream_t s);
 void launch_scan_reduce(const Dev& d, hipStream_t s);
-void launch_scan_top(const Dev& d, hipStream_t s);
 void launch_scan_down(const Dev& d, hipStream_t s);
 void launch_scatter(const Dev& d, int cur, int record, hipStream_t s);
 void launch_propose(const Dev& d, int nxt, hipStream_t s);
-void launch_apply(const Dev& d, int nxt, int record, hipStream_t s);
-void launch_births(const Dev& d, int nxt, int record, hipStream_t s);
+void launch_finish(const Dev& d, int nxt, int record, hipStream_t s);
+void launch_close(const Dev& d, int nxt, int record, hipStream_t s);
 void launch_counts(const Dev& d, int cur, hipStream_t s);
 void launch_fill_records(const Dev& d, hipStream_t s);
 

@@ -1,32 +1,47 @@
 // kernels.hip -- the per-step kernels of the molecule-agent update for
-// gfx950 (wave64).  One step (O2..O10 of the step definition) is
+// gfx950 (wave64).  One step (O2..O10 of the step definition) is seven
+// launches:
 //
-//   move      unimolecular draw, Brownian move, boundaries, event effects,
-//             cell key + rank by per-cell atomic count, birth records
-//   scan      exclusive prefix sum of the cell counts (reduce, top, down)
-//   scatter   agents to cell-sorted order in the other buffer, holes and
-//             degraded agents dropped (stream compaction)
-//   propose   nearest eligible partner of each claimer over the cell
-//             stencil, Bernoulli draw, handshake keys into the claim slots
-//   apply     confirmed pairs fire
-//   births    children sorted by parent id, appended with fresh ids; step
-//             bookkeeping
+//   move         one Philox block per agent gives the event draw and the
+//                Brownian step; boundaries, event effects, birth records;
+//                the cell key of the moved position and its rank in the
+//                cell, by one atomic per run of equal keys in a wave (agents
+//                arrive sorted by cell from the previous step, so runs are
+//                long and the atomics spread over many cells)
+//   scan_reduce  per-tile sums of the cell counts
+//   scan_down    each tile adds the sums of the tiles before it, scans its
+//                counts into cell starts and clears them for the next step
+//   scatter      agents to cell order in the other buffer (holes and
+//                degraded agents dropped: stream compaction)
+//   propose      per workgroup, a chunk of sorted agents: its claimers are
+//                compacted in LDS, then each finds the nearest eligible
+//                partner over the 8- or 27-cell stencil, draws its Bernoulli
+//                and writes the handshake keys into both claim slots
+//   finish       per chunk: confirmation and pair products
+//   close        one workgroup: the step's births sorted by parent id and
+//                appended with fresh ids; the step bookkeeping
 //
-// All agent data are structure-of-arrays, one thread per agent, so every
-// streaming access is coalesced.  No kernel here is a dense contraction.
+// No kernel spins or waits on another workgroup, and no hot loop puts many
+// atomics on one address (they serialise at the memory side).  Agent data
+// are structure-of-arrays, so streaming accesses are coalesced.  Nothing
+// here is a dense contraction.
 #include "device_math.hpp"
 #include "engine.hpp"
 
 namespace mabm {
 
-const char* const kKernelNames[kNumKernels] = {"move", "scan_reduce", "scan_top", "scan_down",
-                                               "scatter", "propose", "apply", "births"};
+const char* const kKernelNames[kNumKernels] = {"move",    "scan_reduce", "scan_down", "scatter",
+                                               "propose", "finish",      "close"};
 
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kPChunk = 512;  // sorted agents per workgroup of propose/finish
 
-__device__ __forceinline__ uint32_t grid_blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// lanes strictly below this one
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
 
 // ---------------------------------------------------------------------------
 // O0: initial placement.  Agent i (id i) belongs to the first species whose
@@ -68,9 +83,6 @@ __global__ void __launch_bounds__(kBlock) k_init(Dev d)
     A.z[i] = z;
     A.id[i] = i;
     A.sp[i] = uint8_t(s);
-    d.rkey[i] = kNone;
-    d.revent[i] = kNoEvent;
-    d.rpartner[i] = kNone;
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_records(Dev d)
@@ -129,9 +141,8 @@ __device__ __forceinline__ void push_birth(const Dev& d, uint32_t parent, int sp
 
 // ---------------------------------------------------------------------------
 // move: O2 (event draw), O3 (Brownian step), O4 (boundaries), O5 and the
-// unimolecular part of O8, then the cell key of the moved position and its
-// rank within the cell (atomic count).  Final position and species are
-// written back in place; busy agents are flagged.
+// unimolecular part of O8, then the cell key of the moved position and the
+// agent's rank within its cell.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
 {
@@ -140,135 +151,143 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
     const uint32_t n = ctl->n_slots;
     const uint32_t t = ctl->t;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    __shared__ uint32_t live;
-    if (threadIdx.x == 0) live = 0;
-    __syncthreads();
-    if (i < n) {
-        Agents A = d.a[cur];
-        const uint32_t s = A.sp[i];
-        if (s == kDead) {
-            d.key[i] = kNone;
+    const Agents A = d.a[cur];
+    uint32_t key = kNone;
+    uint32_t s = kDead;
+    if (i < n) s = A.sp[i];
+    if (s != kDead) {
+        const uint32_t id = A.id[i];
+        const float x = A.x[i], y = A.y[i], z = A.z[i];
+        const int c0 = compartment(T, x, y, z);
+        const U4 w = draw(T, id, t, kMove, 0u);
+
+        int ev = -1;
+        const int nu = T.uni_n[s][c0];
+        if (nu) {
+            const uint32_t wu = event_bits(w);
+            for (int j = 0; j < nu; ++j)
+                if (uint64_t(wu) < T.uni_thr[s][c0][j]) {
+                    ev = T.uni_rule[s][c0][j];
+                    break;
+                }
+        }
+
+        float z0, z1, z2;
+        normals3(w, z0, z1, z2);
+        const float sg = T.sigma[s];
+        float x1 = x + sg * z0, y1 = y + sg * z1, w1 = z + sg * z2;
+        if (T.geometry == kBox) {
+            x1 = wrap_box(T, x1);
+            y1 = wrap_box(T, y1);
+            w1 = wrap_box(T, w1);
         } else {
-            atomicAdd(&live, 1u);
-            const uint32_t id = A.id[i];
-            const float x = A.x[i], y = A.y[i], z = A.z[i];
-            const int c0 = compartment(T, x, y, z);
-
-            int ev = -1;
-            const int nu = T.uni_n[s][c0];
-            if (nu) {
-                const uint32_t w = draw(T, id, t, kUni, 0u).w0;
-                for (int j = 0; j < nu; ++j)
-                    if (uint64_t(w) < T.uni_thr[s][c0][j]) {
-                        ev = T.uni_rule[s][c0][j];
-                        break;
-                    }
-            }
-
-            float z0, z1, z2;
-            normals3(T, id, t, z0, z1, z2);
-            const float sg = T.sigma[s];
-            float x1 = x + sg * z0, y1 = y + sg * z1, w1 = z + sg * z2;
-            if (T.geometry == kBox) {
-                x1 = wrap_box(T, x1);
-                y1 = wrap_box(T, y1);
-                w1 = wrap_box(T, w1);
-            } else {
-                const float n2 = sq3(x1, y1, w1);
-                bool reject = n2 > T.Rout2;
-                if (T.geometry == kNested && !reject && (n2 < T.Rin2 ? 0 : 1) != c0) reject = true;
-                if (reject) {
-                    x1 = x;
-                    y1 = y;
-                    w1 = z;
-                }
-            }
-            const uint32_t key = cell_of(T, x1, y1, w1);
-
-            uint32_t fs = s;
-            float fx = x1, fy = y1, fz = w1;
-            bool dies = false;
-            if (ev >= 0) {
-                const RuleDev& R = T.rule[ev];
-                float ux, uy, uz;
-                switch (R.placement) {
-                case kKeep:
-                    if (R.p0 < 0) dies = true;
-                    else fs = uint32_t(R.p0);
-                    break;
-                case kTranslocate: {
-                    const float n2 = sq3(x1, y1, w1);
-                    if (n2 == 0.0f) {
-                        fx = R.target_r;
-                        fy = 0.0f;
-                        fz = 0.0f;
-                    } else {
-                        const float f = R.target_r / __builtin_sqrtf(n2);
-                        fx = x1 * f;
-                        fy = y1 * f;
-                        fz = w1 * f;
-                    }
-                    if (R.p0 >= 0) fs = uint32_t(R.p0);
-                    break;
-                }
-                case kSplit: {
-                    release_offset(T, R, id, t, x1, y1, w1, true, ux, uy, uz);
-                    fs = uint32_t(R.p0);
-                    fx = x1 + ux;
-                    fy = y1 + uy;
-                    fz = w1 + uz;
-                    float cx = x1 - ux, cy = y1 - uy, cz = w1 - uz;
-                    if (T.geometry == kBox) {
-                        fx = wrap_box(T, fx);
-                        fy = wrap_box(T, fy);
-                        fz = wrap_box(T, fz);
-                        cx = wrap_box(T, cx);
-                        cy = wrap_box(T, cy);
-                        cz = wrap_box(T, cz);
-                    }
-                    push_birth(d, id, R.p1, cx, cy, cz);
-                    break;
-                }
-                default: {  // kEmit
-                    release_offset(T, R, id, t, x1, y1, w1, false, ux, uy, uz);
-                    if (R.p0 >= 0) fs = uint32_t(R.p0);
-                    float cx = x1 + ux, cy = y1 + uy, cz = w1 + uz;
-                    if (T.geometry == kBox) {
-                        cx = wrap_box(T, cx);
-                        cy = wrap_box(T, cy);
-                        cz = wrap_box(T, cz);
-                    }
-                    push_birth(d, id, R.p1, cx, cy, cz);
-                    break;
-                }
-                }
-            }
-            if (dies) {
-                d.key[i] = kNone;
-            } else {
-                A.x[i] = fx;
-                A.y[i] = fy;
-                A.z[i] = fz;
-                A.sp[i] = uint8_t(fs);
-                d.key[i] = key;
-                d.rank[i] = atomicAdd(&d.cell_count[key], 1u);
-                d.flag[i] = ev >= 0 ? 1 : 0;
-                if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
+            const float n2 = sq3(x1, y1, w1);
+            bool reject = n2 > T.Rout2;
+            if (T.geometry == kNested && !reject && (n2 < T.Rin2 ? 0 : 1) != c0) reject = true;
+            if (reject) {
+                x1 = x;
+                y1 = y;
+                w1 = z;
             }
         }
+
+        uint32_t fs = s;
+        float fx = x1, fy = y1, fz = w1;
+        bool dies = false;
+        if (ev >= 0) {
+            const RuleDev& R = T.rule[ev];
+            float ux, uy, uz;
+            switch (R.placement) {
+            case kKeep:
+                if (R.p0 < 0) dies = true;
+                else fs = uint32_t(R.p0);
+                break;
+            case kTranslocate: {
+                const float n2 = sq3(x1, y1, w1);
+                if (n2 == 0.0f) {
+                    fx = R.target_r;
+                    fy = 0.0f;
+                    fz = 0.0f;
+                } else {
+                    const float f = R.target_r / __builtin_sqrtf(n2);
+                    fx = x1 * f;
+                    fy = y1 * f;
+                    fz = w1 * f;
+                }
+                if (R.p0 >= 0) fs = uint32_t(R.p0);
+                break;
+            }
+            case kSplit: {
+                release_offset(T, R, id, t, x1, y1, w1, true, ux, uy, uz);
+                fs = uint32_t(R.p0);
+                fx = x1 + ux;
+                fy = y1 + uy;
+                fz = w1 + uz;
+                float cx = x1 - ux, cy = y1 - uy, cz = w1 - uz;
+                if (T.geometry == kBox) {
+                    fx = wrap_box(T, fx);
+                    fy = wrap_box(T, fy);
+                    fz = wrap_box(T, fz);
+                    cx = wrap_box(T, cx);
+                    cy = wrap_box(T, cy);
+                    cz = wrap_box(T, cz);
+                }
+                push_birth(d, id, R.p1, cx, cy, cz);
+                break;
+            }
+            default: {  // kEmit
+                release_offset(T, R, id, t, x1, y1, w1, false, ux, uy, uz);
+                if (R.p0 >= 0) fs = uint32_t(R.p0);
+                float cx = x1 + ux, cy = y1 + uy, cz = w1 + uz;
+                if (T.geometry == kBox) {
+                    cx = wrap_box(T, cx);
+                    cy = wrap_box(T, cy);
+                    cz = wrap_box(T, cz);
+                }
+                push_birth(d, id, R.p1, cx, cy, cz);
+                break;
+            }
+            }
+        }
+        if (!dies) {
+            key = cell_of(T, x1, y1, w1);
+            A.x[i] = fx;
+            A.y[i] = fy;
+            A.z[i] = fz;
+            A.sp[i] = uint8_t(fs);
+            d.flag[i] = ev >= 0 ? 1 : 0;
+            if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
+        }
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && live) atomicAdd(&ctl->agent_updates, (unsigned long long)live);
+    // Rank within the cell: lanes with equal keys form runs (the input is
+    // cell-sorted); the head of each run adds the run length atomically and
+    // the run's lanes take consecutive ranks.  A key split over several
+    // runs gets several disjoint ranges, so any input order is correct.
+    const int lane = lane_id();
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || key != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int head_lane = 63 - __builtin_clzll(heads & upto);
+    const uint64_t after = heads & ~upto;
+    const int next_head = after ? __builtin_ctzll(after) : 64;
+    uint32_t base = 0;
+    if (head && key != kNone) base = atomicAdd(&d.cell_count[key], uint32_t(next_head - lane));
+    base = __shfl(base, head_lane, 64);
+    if (i < n) {
+        d.key[i] = key;
+        if (key != kNone) d.rank[i] = base + uint32_t(lane - head_lane);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// scan of the cell counts: per-tile sums, one workgroup over the tile sums,
-// per-tile exclusive scan with the tile offset (counts cleared for the next
-// step).
+// scan of the cell counts in two launches, neither of which waits on another
+// workgroup: per-tile sums, then per tile the sum of the earlier tiles'
+// sums, the exclusive scan of its 2048 counts and the clearing of the counts.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = lane_id();
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t u = __shfl_up(v, o, 64);
@@ -277,11 +296,11 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// exclusive scan over a 256-thread block; returns the block total in *total
+// exclusive scan over the 256-thread block; the block total in *total
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
 {
     __shared__ uint32_t wsum[kScanThreads / 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
     const uint32_t inc = wave_incl_scan(v);
     if (lane == 63) wsum[wv] = inc;
     __syncthreads();
@@ -299,60 +318,53 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
 {
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < d.ncells) s += d.cell_count[base + k];
-    uint32_t tot;
-    block_excl_scan(s, &tot);
-    if (threadIdx.x == 0) d.tile_sum[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_scan_top(Dev d)
-{
-    uint32_t carry = 0;
-    for (uint32_t b = 0; b < d.ntiles; b += kScanThreads) {
-        const uint32_t k = b + threadIdx.x;
-        const uint32_t v = k < d.ntiles ? d.tile_sum[k] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
-        if (k < d.ntiles) d.tile_sum[k] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        d.ctl->n_binned = carry;
-        d.cell_start[d.ncells] = carry;
-    }
+    const uint4* cnt4 = reinterpret_cast<const uint4*>(d.cell_count + base);
+    const uint4 a = cnt4[0], b = cnt4[1];
+    uint32_t total;
+    block_excl_scan(a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w, &total);
+    if (threadIdx.x == 0) d.tile_sum[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(Dev d)
 {
-    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t v[kScanItems];
-    uint32_t s = 0;
+    const uint32_t tile = blockIdx.x;
+    uint32_t before = 0;
+    for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += d.tile_sum[k];
+    uint32_t prefix;
+    block_excl_scan(before, &prefix);
+    const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+    uint4* cnt4 = reinterpret_cast<uint4*>(d.cell_count + base);
+    const uint4 a = cnt4[0], b = cnt4[1];
+    const uint32_t v[kScanItems] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) sum += v[k];
+    uint32_t total;
+    uint32_t run = prefix + block_excl_scan(sum, &total);
+    uint32_t out[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        v[k] = base + k < d.ncells ? d.cell_count[base + k] : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t run = d.tile_sum[blockIdx.x] + block_excl_scan(s, &tot);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < d.ncells) {
-            d.cell_start[base + k] = run;
-            d.cell_count[base + k] = 0u;
-        }
+        out[k] = run;
         run += v[k];
+    }
+    uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + base);
+    st4[0] = uint4{out[0], out[1], out[2], out[3]};
+    st4[1] = uint4{out[4], out[5], out[6], out[7]};
+    cnt4[0] = uint4{0u, 0u, 0u, 0u};
+    cnt4[1] = uint4{0u, 0u, 0u, 0u};
+    if (tile == d.ntiles - 1 && threadIdx.x == 0) {
+        d.cell_start[d.ntiles * kScanTile] = prefix + total;
+        d.ctl->n_binned = prefix + total;
     }
 }
 
 // ---------------------------------------------------------------------------
-// scatter: binned agents to cell order in the other buffer (O9 compaction
-// of holes and degraded agents happens here: they carry no key).
+// scatter: binned agents to cell order in the other buffer, with their busy
+// flag and the claimer bit (non-busy agent of a claiming species).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
 {
+    const Tables& T = *d.tab;
     const uint32_t n = d.ctl->n_slots;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -361,12 +373,15 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
     const uint32_t j = d.cell_start[key] + d.rank[i];
     const Agents A = d.a[cur];
     const Agents B = d.a[cur ^ 1];
+    const uint8_t sp = A.sp[i];
+    const uint8_t fl = d.flag[i];
+    const bool claim = !fl && T.claimer[sp];
     B.x[j] = A.x[i];
     B.y[j] = A.y[i];
     B.z[j] = A.z[i];
     B.id[j] = A.id[i];
-    B.sp[j] = A.sp[i];
-    d.sflag[j] = d.flag[i];
+    B.sp[j] = sp;
+    d.sflag[j] = uint8_t(fl | (claim ? kClaimerBit : 0u));
     d.slot[j] = ~0ull;
     if (record) {
         d.rkey[j] = key;
@@ -375,10 +390,37 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
     }
 }
 
+// Compact, in LDS, the agents of this workgroup's chunk [first, last) that
+// satisfy `pred` (one LDS atomic per wave).  Returns the list length.
+template <class Pred>
+__device__ __forceinline__ uint32_t compact_chunk(uint32_t first, uint32_t last, uint32_t* list,
+                                                  uint32_t* count, Pred pred)
+{
+    if (threadIdx.x == 0) *count = 0;
+    __syncthreads();
+    for (uint32_t k = first + threadIdx.x; k < last; k += kBlock) {
+        const bool c = pred(k);
+        const uint64_t m = __ballot(c);
+        if (m) {
+            const int leader = __builtin_ctzll(m);
+            uint32_t base = 0;
+            if (lane_id() == leader) base = atomicAdd(count, uint32_t(__builtin_popcountll(m)));
+            base = __shfl(base, leader, 64);
+            if (c) list[base + __builtin_popcountll(m & lanes_below())] = k;
+        }
+    }
+    __syncthreads();
+    return *count;
+}
+
 // ---------------------------------------------------------------------------
-// propose (O7): for each non-busy claimer, the eligible partner minimising
-// (d^2, id) over the 8-cell (h >= 2 R_max) or 27-cell stencil; a Bernoulli
-// draw; both claim slots take the handshake key by atomic minimum.
+// propose (O7): for each claimer, the eligible partner minimising (d^2, id)
+// over the 8-cell (h >= 2 R_max) or 27-cell stencil, then a Bernoulli draw,
+// then the handshake key into both claim slots by atomic minimum.  A
+// workgroup takes 512 sorted agents; their claimers are searched by
+// subgroups of 8 (or 32) lanes, one stencil cell per lane, and the lanes'
+// best candidates are reduced by shuffles, so each claimer's dependent
+// chain of loads is a few round trips long.
 // ---------------------------------------------------------------------------
 struct Best {
     uint32_t idx, id;
@@ -386,157 +428,156 @@ struct Best {
     int rule;
 };
 
-__device__ __forceinline__ void scan_cell(const Dev& d, const Tables& T, const Agents& A,
-                                          uint32_t cell, uint32_t self, uint32_t s, float x,
-                                          float y, float z, int comp, Best& b)
+__device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Agents& A,
+                                         uint32_t k, uint32_t self, uint32_t s, float x,
+                                         float y, float z, int comp, Best& b)
 {
-    const uint32_t e = d.cell_start[cell + 1];
-    for (uint32_t k = d.cell_start[cell]; k < e; ++k) {
-        if (k == self) continue;
-        const int r = T.rule_of[s][A.sp[k]];
-        if (r < 0 || d.sflag[k]) continue;
-        const float bx = A.x[k], by = A.y[k], bz = A.z[k];
-        if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) continue;
-        float dx = bx - x, dy = by - y, dz = bz - z;
-        if (T.geometry == kBox) {
-            if (dx > T.halfL) dx -= T.L; else if (dx < -T.halfL) dx += T.L;
-            if (dy > T.halfL) dy -= T.L; else if (dy < -T.halfL) dy += T.L;
-            if (dz > T.halfL) dz -= T.L; else if (dz < -T.halfL) dz += T.L;
-        }
-        const float d2 = dx * dx + dy * dy + dz * dz;
-        if (!(d2 <= T.rule[r].r2)) continue;
-        const uint32_t bid = A.id[k];
-        if (b.idx == kNone || d2 < b.d2 || (d2 == b.d2 && bid < b.id)) {
-            b.idx = k;
-            b.id = bid;
-            b.d2 = d2;
-            b.rule = r;
-        }
+    const uint32_t sk = A.sp[k];
+    const uint8_t fk = d.sflag[k];
+    const float bx = A.x[k], by = A.y[k], bz = A.z[k];
+    const uint32_t bid = A.id[k];
+    const int r = T.rule_of[s][sk];
+    if (k == self || r < 0 || (fk & kBusyBit)) return;
+    if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
+    float dx = bx - x, dy = by - y, dz = bz - z;
+    if (T.geometry == kBox) {
+        if (dx > T.halfL) dx -= T.L; else if (dx < -T.halfL) dx += T.L;
+        if (dy > T.halfL) dy -= T.L; else if (dy < -T.halfL) dy += T.L;
+        if (dz > T.halfL) dz -= T.L; else if (dz < -T.halfL) dz += T.L;
+    }
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    if (!(d2 <= T.rule[r].r2)) return;
+    if (b.idx == kNone || d2 < b.d2 || (d2 == b.d2 && bid < b.id)) {
+        b.idx = k;
+        b.id = bid;
+        b.d2 = d2;
+        b.rule = r;
+    }
+}
+
+// Lexicographic minimum of (d^2, id) over the lanes of a subgroup of
+// `width` lanes (xor butterfly within the subgroup).
+__device__ __forceinline__ void reduce_best(Best& b, int width)
+{
+    for (int o = width >> 1; o >= 1; o >>= 1) {
+        Best c;
+        c.idx = __shfl_xor(b.idx, o, width);
+        c.id = __shfl_xor(b.id, o, width);
+        c.d2 = __shfl_xor(b.d2, o, width);
+        c.rule = __shfl_xor(b.rule, o, width);
+        if (c.idx != kNone && (b.idx == kNone || c.d2 < b.d2 || (c.d2 == b.d2 && c.id < b.id)))
+            b = c;
     }
 }
 
 __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
 {
+    __shared__ uint32_t list[kPChunk];
+    __shared__ uint32_t count;
     const Tables& T = *d.tab;
     const uint32_t n = d.ctl->n_binned;
     const uint32_t t = d.ctl->t;
-    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
+    const uint32_t first = blockIdx.x * kPChunk;
+    if (first >= n) return;
+    const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
+    const uint32_t nl = compact_chunk(first, last, list, &count,
+                                      [&](uint32_t k) { return (d.sflag[k] & kClaimerBit) != 0; });
     const Agents A = d.a[nxt];
-    const uint32_t s = A.sp[j];
-    uint32_t out = kNone;
-    if (!d.sflag[j] && T.claimer[s]) {
+    const int G = int(T.G);
+    const bool periodic = T.geometry == kBox;
+    // a subgroup of `width` lanes per claimer, one stencil cell per lane
+    const int width = T.stencil8 ? 8 : 32;
+    const int ncell = T.stencil8 ? 8 : 27;
+    const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
+    const int nsub = kBlock / width;
+    for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
+        const uint32_t j = list[q];
+        const uint32_t s = A.sp[j];
         const float x = A.x[j], y = A.y[j], z = A.z[j];
         const int comp = compartment(T, x, y, z);
-        const int G = int(T.G);
-        int c[3], lo[3], hi[3], step[3];
-        const float p[3] = {x, y, z};
-        for (int a = 0; a < 3; ++a) {
-            c[a] = int(cell_coord(T, p[a]));
-            if (T.stencil8) {
-                const float f = (p[a] - T.lo) * T.inv_h - float(c[a]);
-                lo[a] = 0;
-                hi[a] = 1;
-                step[a] = f < 0.5f ? -1 : 1;
-            } else {
-                lo[a] = -1;
-                hi[a] = 1;
-                step[a] = 1;
+        Best b{kNone, 0u, 0.0f, -1};
+        if (li < ncell) {
+            const float p[3] = {x, y, z};
+            const int o[3] = {li % 3, (li / 3) % 3, li / 9};
+            const int o8[3] = {li & 1, (li >> 1) & 1, li >> 2};
+            int cc[3];
+            bool inside = true;
+            for (int a = 0; a < 3; ++a) {
+                const int c = int(cell_coord(T, p[a]));
+                int v;
+                if (T.stencil8) {
+                    // the neighbour on the side of the cell the point is nearer
+                    const float f = (p[a] - T.lo) * T.inv_h - float(c);
+                    v = c + o8[a] * (f < 0.5f ? -1 : 1);
+                } else {
+                    v = c + o[a] - 1;
+                }
+                if (periodic) v = (v + G) % G;
+                else if (v < 0 || v >= G) inside = false;
+                cc[a] = v;
+            }
+            if (inside) {
+                const uint32_t cell = uint32_t(cc[0]) + T.G * (uint32_t(cc[1]) + T.G * uint32_t(cc[2]));
+                const uint32_t e = d.cell_start[cell + 1];
+                for (uint32_t k = d.cell_start[cell]; k < e; ++k)
+                    consider(d, T, A, k, j, s, x, y, z, comp, b);
             }
         }
-        Best b{kNone, 0u, 0.0f, -1};
-        const bool periodic = T.geometry == kBox;
-        for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-            int cz = c[2] + oz * step[2];
-            if (periodic) cz = (cz + G) % G; else if (cz < 0 || cz >= G) continue;
-            for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-                int cy = c[1] + oy * step[1];
-                if (periodic) cy = (cy + G) % G; else if (cy < 0 || cy >= G) continue;
-                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-                    int cx = c[0] + ox * step[0];
-                    if (periodic) cx = (cx + G) % G; else if (cx < 0 || cx >= G) continue;
-                    const uint32_t cell = uint32_t(cx) + T.G * (uint32_t(cy) + T.G * uint32_t(cz));
-                    scan_cell(d, T, A, cell, j, s, x, y, z, comp, b);
+        reduce_best(b, width);
+        if (li == 0) {
+            uint32_t out = kNone;
+            if (b.idx != kNone) {
+                const uint32_t ida = A.id[j];
+                const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
+                if (uint64_t(w) < T.rule[b.rule].thr) {
+                    const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
+                    const unsigned long long pr =
+                        (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
+                    atomicMin(&d.slot[j], pr | b.id);
+                    atomicMin(&d.slot[b.idx], pr | ida);
+                    out = b.idx;
                 }
             }
+            d.prop[j] = out;
         }
-        if (b.idx != kNone) {
-            const uint32_t ida = A.id[j];
-            const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
-            if (uint64_t(w) < T.rule[b.rule].thr) {
-                const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
-                const unsigned long long pr =
-                    (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
-                atomicMin(&d.slot[j], pr | b.id);
-                atomicMin(&d.slot[b.idx], pr | ida);
-                out = b.idx;
-            }
-        }
-    }
-    d.prop[j] = out;
-}
-
-// ---------------------------------------------------------------------------
-// apply (O7 confirmation, O8 pair products).  Only the claimer of a
-// confirmed pair writes, and of a mutual (homotypic) pair only the lower id.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_apply(Dev d, int nxt, int record)
-{
-    const Tables& T = *d.tab;
-    const uint32_t n = d.ctl->n_binned;
-    const uint32_t t = d.ctl->t;
-    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t b = d.prop[j];
-    if (b == kNone) return;
-    const Agents A = d.a[nxt];
-    const uint32_t ida = A.id[j], idb = A.id[b];
-    const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
-    const unsigned long long pr = (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
-    if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) return;
-    if (d.prop[b] == j && idb < ida) return;
-    const RuleDev& R = T.rule[T.rule_of[A.sp[j]][A.sp[b]]];
-    A.sp[j] = R.p0 < 0 ? kDead : uint8_t(R.p0);
-    A.sp[b] = R.p1 < 0 ? kDead : uint8_t(R.p1);
-    if (record) {
-        d.rpartner[j] = idb;
-        d.rpartner[b] = ida;
     }
 }
 
 // ---------------------------------------------------------------------------
-// births (O9, O10): one workgroup sorts this step's birth records by parent
-// id (bitonic, in LDS), appends the children after the binned agents with
-// ids next_id, next_id + 1, ..., and advances the step bookkeeping.
+// finish: O7 confirmation and O8 pair products (only the claimer of a
+// confirmed pair writes, and of a mutual homotypic pair only the lower id).
+// close (one workgroup): O9/O10, the step's births sorted by parent id
+// (bitonic, LDS), appended after the binned agents with ids next_id,
+// next_id + 1, ..., and the step bookkeeping.
 // ---------------------------------------------------------------------------
-constexpr int kBirthThreads = 1024;
+constexpr int kCloseThreads = 1024;
 
-__global__ void __launch_bounds__(kBirthThreads) k_births(Dev d, int nxt, int record)
+__global__ void __launch_bounds__(kCloseThreads) k_close(Dev d, int nxt, int record)
 {
     __shared__ uint32_t skey[kMaxBirthsPerStep];
     __shared__ uint32_t sidx[kMaxBirthsPerStep];
     Ctl* ctl = d.ctl;
     const uint32_t nbin = ctl->n_binned;
     uint32_t nb = ctl->n_births;
-    bool overflow = false;
+    uint32_t err = 0;
     if (nb > kMaxBirthsPerStep) {
-        overflow = true;
+        err = kErrBirths;
         nb = 0;
     } else if (uint64_t(nbin) + nb > d.capacity) {
-        overflow = true;
+        err = kErrCapacity;
         nb = 0;
     }
     if (nb > 0) {
         uint32_t np = 1;
         while (np < nb) np <<= 1;
-        for (uint32_t k = threadIdx.x; k < np; k += kBirthThreads) {
+        for (uint32_t k = threadIdx.x; k < np; k += kCloseThreads) {
             skey[k] = k < nb ? d.births[k].parent : 0xFFFFFFFFu;
             sidx[k] = k;
         }
         __syncthreads();
         for (uint32_t size = 2; size <= np; size <<= 1) {
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t k = threadIdx.x; k < np; k += kBirthThreads) {
+                for (uint32_t k = threadIdx.x; k < np; k += kCloseThreads) {
                     const uint32_t o = k ^ stride;
                     if (o > k) {
                         const bool up = (k & size) == 0;
@@ -555,7 +596,7 @@ __global__ void __launch_bounds__(kBirthThreads) k_births(Dev d, int nxt, int re
         }
         const Agents A = d.a[nxt];
         const uint32_t base_id = ctl->next_id;
-        for (uint32_t r = threadIdx.x; r < nb; r += kBirthThreads) {
+        for (uint32_t r = threadIdx.x; r < nb; r += kCloseThreads) {
             const Birth bb = d.births[sidx[r]];
             const uint32_t j = nbin + r;
             A.x[j] = bb.x;
@@ -572,12 +613,59 @@ __global__ void __launch_bounds__(kBirthThreads) k_births(Dev d, int nxt, int re
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (overflow) atomicOr(&ctl->err, kErrCapacity);
+        if (err) atomicOr(&ctl->err, err);
+        const uint32_t holes = __hip_atomic_load(&ctl->holes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctl->agent_updates += ctl->live;
+        ctl->live = nbin - holes + nb;
+        ctl->holes = 0u;
         ctl->n_slots = nbin + nb;
         ctl->next_id += nb;
-        ctl->n_births = 0;
-        ctl->t += 1;
+        ctl->n_births = 0u;
+        ctl->t += 1u;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int nxt, int record)
+{
+    __shared__ uint32_t list[kPChunk];
+    __shared__ uint32_t count, s_holes;
+    const Tables& T = *d.tab;
+    Ctl* ctl = d.ctl;
+    const uint32_t n = ctl->n_binned;
+    const uint32_t t = ctl->t;
+    const uint32_t first = blockIdx.x * kPChunk;
+    if (threadIdx.x == 0) s_holes = 0;
+    if (first < n) {
+        const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
+        const uint32_t nl = compact_chunk(first, last, list, &count, [&](uint32_t k) {
+            return (d.sflag[k] & kClaimerBit) && d.prop[k] != kNone;
+        });
+        const Agents A = d.a[nxt];
+        for (uint32_t q = threadIdx.x; q < nl; q += kBlock) {
+            const uint32_t j = list[q];
+            const uint32_t b = d.prop[j];
+            const uint32_t ida = A.id[j], idb = A.id[b];
+            const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
+            const unsigned long long pr =
+                (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
+            if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) continue;
+            // b proposed too only if it carries the claimer bit (its prop is
+            // then this step's); a mutual pair fires once, from the lower
+            // id.  Species are read only once this thread owns the pair.
+            if (idb < ida && (d.sflag[b] & kClaimerBit) && d.prop[b] == j) continue;
+            const RuleDev& R = T.rule[T.rule_of[A.sp[j]][A.sp[b]]];
+            A.sp[j] = R.p0 < 0 ? kDead : uint8_t(R.p0);
+            A.sp[b] = R.p1 < 0 ? kDead : uint8_t(R.p1);
+            const uint32_t h = (R.p0 < 0 ? 1u : 0u) + (R.p1 < 0 ? 1u : 0u);
+            if (h) atomicAdd(&s_holes, h);
+            if (record) {
+                d.rpartner[j] = idb;
+                d.rpartner[b] = ida;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes, s_holes);
 }
 
 // per-species counts of live agents (LDS histogram, one atomic per species
@@ -606,11 +694,11 @@ __global__ void k_zero_counts(Dev d)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// launch entry points.  Agent-indexed kernels are sized for the capacity
-// and read the live sizes from the control block, so a step needs no host
-// synchronisation.
+// launch entry points.  Agent-indexed kernels are sized for the capacity and
+// read the live sizes from the control block, so a step needs no host
+// synchronisation and can be captured in a graph.
 // ---------------------------------------------------------------------------
-static inline unsigned blocks_for(uint32_t n) { return (n + kBlock - 1) / kBlock; }
+static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
 {
@@ -628,7 +716,6 @@ void launch_scan_reduce(const Dev& d, hipStream_t s)
 {
     k_scan_reduce<<<d.ntiles, kScanThreads, 0, s>>>(d);
 }
-void launch_scan_top(const Dev& d, hipStream_t s) { k_scan_top<<<1, kScanThreads, 0, s>>>(d); }
 void launch_scan_down(const Dev& d, hipStream_t s)
 {
     k_scan_down<<<d.ntiles, kScanThreads, 0, s>>>(d);
@@ -637,24 +724,24 @@ void launch_scatter(const Dev& d, int cur, int record, hipStream_t s)
 {
     k_scatter<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur, record);
 }
+static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 void launch_propose(const Dev& d, int nxt, hipStream_t s)
 {
-    k_propose<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, nxt);
+    k_propose<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, nxt);
 }
-void launch_apply(const Dev& d, int nxt, int record, hipStream_t s)
+void launch_finish(const Dev& d, int nxt, int record, hipStream_t s)
 {
-    k_apply<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, nxt, record);
+    k_finish<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, nxt, record);
 }
-void launch_births(const Dev& d, int nxt, int record, hipStream_t s)
+void launch_close(const Dev& d, int nxt, int record, hipStream_t s)
 {
-    k_births<<<1, kBirthThreads, 0, s>>>(d, nxt, record);
+    k_close<<<1, kCloseThreads, 0, s>>>(d, nxt, record);
 }
 void launch_counts(const Dev& d, int cur, hipStream_t s)
 {
     k_zero_counts<<<1, 64, 0, s>>>(d);
     unsigned nb = blocks_for(d.capacity);
     if (nb > 2048) nb = 2048;
-    if (nb == 0) nb = 1;
     k_counts<<<nb, kBlock, 0, s>>>(d, cur);
 }
 
