@@ -26,19 +26,20 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 # Algorithmic bytes per launch of each step kernel: bytes per live agent (a),
 # per claimer (q) and per cell of the spatial hash (c) that the kernel must
-# read or write at least once for its function.
-#   move:    reads x, y, z, id, species (17 B); writes x, y, z, species (13),
-#            cell key (4), in-cell rank (4), busy flag (1)            = 39 B/agent
+# read or write at least once for its function.  An agent is a 16-byte
+# record {x, y, z, species|flags} plus a 4-byte id.
+#   move:        reads record + id (20); writes record (16) and the
+#                (cell key, rank) pair (8)                           = 44 B/agent
 #   scan_reduce: reads the count                                     =  4 B/cell
-#   scan_down:   reads the count, writes the start, clears the count =  12 B/cell
-#   scatter: reads key, rank, 17 B state, flag, cell start (30); writes 17 B
-#            state, flag, claim slot (26)                              = 56 B/agent
-#   propose: flags of the chunk (1 B/agent); per claimer its position,
-#            species and id (17) and its proposal (4)               = 1 B/agent + 21 B/claimer
-#   finish:  flags of the chunk (1 B/agent); per claimer its proposal (4)
-#                                                                   = 1 B/agent + 4 B/claimer
-KERNEL_BYTES = {"move": (39, 0, 0), "scan_reduce": (0, 0, 4), "scan_down": (0, 0, 12),
-                "scatter": (56, 0, 0), "propose": (1, 21, 0), "finish": (1, 4, 0),
+#   scan_down:   reads the count, writes the start, clears the count = 12 B/cell
+#   scatter:     reads (key, rank), record, id, cell start (32);
+#                writes record, id, claimer byte, claim slot (29)    = 61 B/agent
+#   propose:     claimer byte of the chunk (1 B/agent); per claimer its
+#                record and id (20) and its proposal (4)             = 1 B/agent + 24 B/claimer
+#   finish:      claimer byte of the chunk (1 B/agent); per claimer its
+#                proposal (4)                                        = 1 B/agent + 4 B/claimer
+KERNEL_BYTES = {"move": (44, 0, 0), "scan_reduce": (0, 0, 4), "scan_down": (0, 0, 12),
+                "scatter": (61, 0, 0), "propose": (1, 24, 0), "finish": (1, 4, 0),
                 "close": (0, 0, 0)}
 
 

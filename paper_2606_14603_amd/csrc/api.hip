@@ -67,8 +67,8 @@ bool config_ok(const mabm_config* c, std::string& why)
 
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
-    size_t ctl, tab, agents[2][5], key, rank, flag, event, sflag, cell_count, cell_start,
-        tile_sum, slot, prop, rkey, revent, rpartner, births, counts, total;
+    size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_sum, slot,
+        prop, rkey, revent, rpartner, births, counts, total;
     uint32_t ncells, ntiles;
 };
 
@@ -88,17 +88,12 @@ Layout make_layout(const mabm_config& c)
     L.ctl = take(sizeof(Ctl));
     L.tab = take(sizeof(Tables));
     for (int b = 0; b < 2; ++b) {
-        L.agents[b][0] = take(cap * 4);
-        L.agents[b][1] = take(cap * 4);
-        L.agents[b][2] = take(cap * 4);
-        L.agents[b][3] = take(cap * 4);
-        L.agents[b][4] = take(cap);
+        L.rec[b] = take(cap * 16);
+        L.id[b] = take(cap * 4);
     }
-    L.key = take(cap * 4);
-    L.rank = take(cap * 4);
-    L.flag = take(cap);
+    L.kr = take(cap * 8);
     L.event = take(cap);
-    L.sflag = take(cap);
+    L.sclaim = take(cap);
     const size_t padded = (size_t)L.ntiles * kScanTile;  // whole scan tiles
     L.cell_count = take(padded * 4);
     L.cell_start = take((padded + 1) * 4);
@@ -298,17 +293,12 @@ void fill_dev(mabm_sim* s)
     d.ctl = (Ctl*)(A + L.ctl);
     d.tab = (const Tables*)(A + L.tab);
     for (int b = 0; b < 2; ++b) {
-        d.a[b].x = (float*)(A + L.agents[b][0]);
-        d.a[b].y = (float*)(A + L.agents[b][1]);
-        d.a[b].z = (float*)(A + L.agents[b][2]);
-        d.a[b].id = (uint32_t*)(A + L.agents[b][3]);
-        d.a[b].sp = (uint8_t*)(A + L.agents[b][4]);
+        d.a[b].rec = (uint4*)(A + L.rec[b]);
+        d.a[b].id = (uint32_t*)(A + L.id[b]);
     }
-    d.key = (uint32_t*)(A + L.key);
-    d.rank = (uint32_t*)(A + L.rank);
-    d.flag = A + L.flag;
+    d.kr = (uint2*)(A + L.kr);
     d.event = A + L.event;
-    d.sflag = A + L.sflag;
+    d.sclaim = A + L.sclaim;
     d.cell_count = (uint32_t*)(A + L.cell_count);
     d.cell_start = (uint32_t*)(A + L.cell_start);
     d.tile_sum = (uint32_t*)(A + L.tile_sum);
@@ -605,15 +595,12 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
     if (st != MABM_OK) return st;
     const uint32_t n = ctl.n_slots;
     const Agents& A = s->dev.a[s->parity];
-    std::vector<float> hx(n), hy(n), hz(n);
+    std::vector<uint4> hr(n);
     std::vector<uint32_t> hid(n), hk(n), hp(n);
     std::vector<uint8_t> hs(n), he(n);
     if (n) {
-        HIP_OK(s, hipMemcpyAsync(hx.data(), A.x, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hy.data(), A.y, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hz.data(), A.z, n * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hr.data(), A.rec, (size_t)n * 16, hipMemcpyDeviceToHost, s->stream));
         HIP_OK(s, hipMemcpyAsync(hid.data(), A.id, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hs.data(), A.sp, n, hipMemcpyDeviceToHost, s->stream));
         HIP_OK(s, hipMemcpyAsync(hk.data(), s->dev.rkey, n * 4, hipMemcpyDeviceToHost, s->stream));
         HIP_OK(s, hipMemcpyAsync(he.data(), s->dev.revent, n, hipMemcpyDeviceToHost, s->stream));
         HIP_OK(s, hipMemcpyAsync(hp.data(), s->dev.rpartner, n * 4, hipMemcpyDeviceToHost, s->stream));
@@ -621,8 +608,10 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
     }
     std::vector<uint32_t> idx;
     idx.reserve(n);
-    for (uint32_t i = 0; i < n; ++i)
+    for (uint32_t i = 0; i < n; ++i) {
+        hs[i] = (uint8_t)(hr[i].w & 0xFFu);
         if (hs[i] != kDead) idx.push_back(i);
+    }
     if (idx.size() > capacity) return fail(s, MABM_E_INVALID, "export buffer smaller than the live agents");
     std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return hid[a] < hid[b]; });
     const bool rec = (s->cfg.flags & MABM_FLAG_RECORD) != 0;
@@ -630,9 +619,9 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
         const uint32_t i = idx[k];
         if (id) id[k] = hid[i];
         if (species) species[k] = hs[i];
-        if (x) x[k] = hx[i];
-        if (y) y[k] = hy[i];
-        if (z) z[k] = hz[i];
+        if (x) std::memcpy(&x[k], &hr[i].x, 4);
+        if (y) std::memcpy(&y[k], &hr[i].y, 4);
+        if (z) std::memcpy(&z[k], &hr[i].z, 4);
         if (key) key[k] = rec ? hk[i] : MABM_NONE;
         if (event) event[k] = (rec && he[i] != kNoEvent) ? (int32_t)he[i] : -1;
         if (partner) partner[k] = rec ? hp[i] : MABM_NONE;
@@ -664,12 +653,16 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
     mabm_status st = finalize(s, false);
     if (st != MABM_OK) return st;
     const Agents& A = s->dev.a[0];
+    std::vector<uint4> hr(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        std::memcpy(&hr[i].x, &x[i], 4);
+        std::memcpy(&hr[i].y, &y[i], 4);
+        std::memcpy(&hr[i].z, &z[i], 4);
+        hr[i].w = sp[i];
+    }
     if (n) {
-        HIP_OK(s, hipMemcpyAsync(A.x, x, n * 4, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(s, hipMemcpyAsync(A.y, y, n * 4, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(s, hipMemcpyAsync(A.z, z, n * 4, hipMemcpyHostToDevice, s->stream));
+        HIP_OK(s, hipMemcpyAsync(A.rec, hr.data(), (size_t)n * 16, hipMemcpyHostToDevice, s->stream));
         HIP_OK(s, hipMemcpyAsync(A.id, id, n * 4, hipMemcpyHostToDevice, s->stream));
-        HIP_OK(s, hipMemcpyAsync(A.sp, sp, n, hipMemcpyHostToDevice, s->stream));
     }
     Ctl ctl{};
     ctl.t = t;

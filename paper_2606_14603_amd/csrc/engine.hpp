@@ -14,8 +14,13 @@ constexpr int kMaxRules = 255;
 constexpr int kMaxUni = 8;        // unimolecular rules per (species, compartment)
 constexpr uint8_t kDead = 0xFF;   // species byte of a consumed agent (hole)
 constexpr uint8_t kNoEvent = 0xFF;
-constexpr uint8_t kBusyBit = 1;     // sorted flag: had a unimolecular event
-constexpr uint8_t kClaimerBit = 2;  // sorted flag: on this step's claimer list
+// An agent is a 16-byte record {x, y, z, meta} (position bits, then
+// species in bits 0-7 and this step's flags in bits 8-15) plus its id in a
+// separate array.
+constexpr uint32_t kMetaBusy = 1u << 8;     // had a unimolecular event this step
+constexpr uint32_t kMetaClaimer = 1u << 9;  // non-busy agent of a claiming species
+constexpr int kMetaSpeciesByte = 12;        // byte offset of the species in a record
+constexpr int kMetaFlagsByte = 13;          // byte offset of the flags in a record
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxBirthsPerStep = 4096;  // births sorted by one workgroup
 constexpr int kScanItems = 8;                 // cells per thread in the scan
@@ -79,20 +84,17 @@ struct Birth {
 };
 
 struct Agents {
-    float *x, *y, *z;
+    uint4* rec;
     uint32_t* id;
-    uint8_t* sp;
 };
 
 struct Dev {
     Ctl* ctl;
     const Tables* tab;
     Agents a[2];          // ping-pong agent arrays
-    uint32_t* key;        // per pre-sort slot: cell key (kNone: not binned)
-    uint32_t* rank;       // per pre-sort slot: rank within its cell
-    uint8_t* flag;        // per pre-sort slot: 1 = busy (had an event)
+    uint2* kr;            // per pre-sort slot: cell key (kNone: not binned), rank in cell
     uint8_t* event;       // per pre-sort slot: event rule (record mode)
-    uint8_t* sflag;       // per sorted agent: kBusyBit | kClaimerBit
+    uint8_t* sclaim;      // per sorted agent: 1 = claimer this step
     uint32_t* cell_count;  // ncells rounded up to whole scan tiles
     uint32_t* cell_start;  // padded ncells + 1
     uint32_t* tile_sum;    // per scan tile

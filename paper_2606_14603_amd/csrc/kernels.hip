@@ -13,18 +13,21 @@
 //                counts into cell starts and clears them for the next step
 //   scatter      agents to cell order in the other buffer (holes and
 //                degraded agents dropped: stream compaction)
-//   propose      per workgroup, a chunk of sorted agents: its claimers are
-//                compacted in LDS, then each finds the nearest eligible
-//                partner over the 8- or 27-cell stencil, draws its Bernoulli
-//                and writes the handshake keys into both claim slots
+//   propose      per workgroup, a chunk of 512 sorted agents: its claimers
+//                are compacted in LDS, then each is searched by a subgroup
+//                of lanes, one stencil cell per lane, for the nearest
+//                eligible partner; Bernoulli draw; handshake keys into both
+//                claim slots
 //   finish       per chunk: confirmation and pair products
 //   close        one workgroup: the step's births sorted by parent id and
 //                appended with fresh ids; the step bookkeeping
 //
-// No kernel spins or waits on another workgroup, and no hot loop puts many
-// atomics on one address (they serialise at the memory side).  Agent data
-// are structure-of-arrays, so streaming accesses are coalesced.  Nothing
-// here is a dense contraction.
+// An agent is a 16-byte record {x, y, z, meta} plus a 4-byte id, so a
+// streaming kernel moves whole records with 16-byte accesses and a candidate
+// check in the neighbour search is one 16-byte gather.  No kernel spins or
+// waits on another workgroup, and no hot loop puts many atomics on one
+// address (they serialise at the memory side).  Nothing here is a dense
+// contraction.
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -42,6 +45,21 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // lanes strictly below this one
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint4 make_rec(float x, float y, float z, uint32_t meta)
+{
+    return uint4{__float_as_uint(x), __float_as_uint(y), __float_as_uint(z), meta};
+}
+
+__device__ __forceinline__ void set_species(const Agents& A, uint32_t j, uint32_t s)
+{
+    reinterpret_cast<uint8_t*>(A.rec + j)[kMetaSpeciesByte] = uint8_t(s);
+}
+
+__device__ __forceinline__ uint32_t flags_of(const Agents& A, uint32_t j)
+{
+    return uint32_t(reinterpret_cast<const uint8_t*>(A.rec + j)[kMetaFlagsByte]) << 8;
+}
 
 // ---------------------------------------------------------------------------
 // O0: initial placement.  Agent i (id i) belongs to the first species whose
@@ -77,12 +95,9 @@ __global__ void __launch_bounds__(kBlock) k_init(Dev d)
         }
     }
     if (!ok) atomicOr(&d.ctl->err, kErrPlacement);
-    Agents A = d.a[0];
-    A.x[i] = x;
-    A.y[i] = y;
-    A.z[i] = z;
+    const Agents A = d.a[0];
+    A.rec[i] = make_rec(x, y, z, uint32_t(s));
     A.id[i] = i;
-    A.sp[i] = uint8_t(s);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_records(Dev d)
@@ -153,11 +168,15 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     const Agents A = d.a[cur];
     uint32_t key = kNone;
-    uint32_t s = kDead;
-    if (i < n) s = A.sp[i];
+    uint4 r = {0u, 0u, 0u, kDead};
+    uint32_t id = 0;
+    if (i < n) {
+        r = A.rec[i];
+        id = A.id[i];
+    }
+    const uint32_t s = r.w & 0xFFu;
     if (s != kDead) {
-        const uint32_t id = A.id[i];
-        const float x = A.x[i], y = A.y[i], z = A.z[i];
+        const float x = __uint_as_float(r.x), y = __uint_as_float(r.y), z = __uint_as_float(r.z);
         const int c0 = compartment(T, x, y, z);
         const U4 w = draw(T, id, t, kMove, 0u);
 
@@ -251,11 +270,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
         }
         if (!dies) {
             key = cell_of(T, x1, y1, w1);
-            A.x[i] = fx;
-            A.y[i] = fy;
-            A.z[i] = fz;
-            A.sp[i] = uint8_t(fs);
-            d.flag[i] = ev >= 0 ? 1 : 0;
+            A.rec[i] = make_rec(fx, fy, fz, fs | (ev >= 0 ? kMetaBusy : 0u));
             if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
         }
     }
@@ -274,10 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
     uint32_t base = 0;
     if (head && key != kNone) base = atomicAdd(&d.cell_count[key], uint32_t(next_head - lane));
     base = __shfl(base, head_lane, 64);
-    if (i < n) {
-        d.key[i] = key;
-        if (key != kNone) d.rank[i] = base + uint32_t(lane - head_lane);
-    }
+    if (i < n) d.kr[i] = uint2{key, base + uint32_t(lane - head_lane)};
 }
 
 // ---------------------------------------------------------------------------
@@ -359,8 +371,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(Dev d)
 }
 
 // ---------------------------------------------------------------------------
-// scatter: binned agents to cell order in the other buffer, with their busy
-// flag and the claimer bit (non-busy agent of a claiming species).
+// scatter: binned agents to cell order in the other buffer; the claimer flag
+// (non-busy agent of a claiming species) is set in the record and in the
+// one-byte array the propose/finish chunks scan.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
 {
@@ -368,23 +381,20 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
     const uint32_t n = d.ctl->n_slots;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint32_t key = d.key[i];
-    if (key == kNone) return;
-    const uint32_t j = d.cell_start[key] + d.rank[i];
+    const uint2 kr = d.kr[i];
+    if (kr.x == kNone) return;
+    const uint32_t j = d.cell_start[kr.x] + kr.y;
     const Agents A = d.a[cur];
     const Agents B = d.a[cur ^ 1];
-    const uint8_t sp = A.sp[i];
-    const uint8_t fl = d.flag[i];
-    const bool claim = !fl && T.claimer[sp];
-    B.x[j] = A.x[i];
-    B.y[j] = A.y[i];
-    B.z[j] = A.z[i];
+    uint4 r = A.rec[i];
+    const bool claim = !(r.w & kMetaBusy) && T.claimer[r.w & 0xFFu];
+    if (claim) r.w |= kMetaClaimer;
+    B.rec[j] = r;
     B.id[j] = A.id[i];
-    B.sp[j] = sp;
-    d.sflag[j] = uint8_t(fl | (claim ? kClaimerBit : 0u));
+    d.sclaim[j] = claim ? 1 : 0;
     d.slot[j] = ~0ull;
     if (record) {
-        d.rkey[j] = key;
+        d.rkey[j] = kr.x;
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
     }
@@ -432,12 +442,10 @@ __device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Ag
                                          uint32_t k, uint32_t self, uint32_t s, float x,
                                          float y, float z, int comp, Best& b)
 {
-    const uint32_t sk = A.sp[k];
-    const uint8_t fk = d.sflag[k];
-    const float bx = A.x[k], by = A.y[k], bz = A.z[k];
-    const uint32_t bid = A.id[k];
-    const int r = T.rule_of[s][sk];
-    if (k == self || r < 0 || (fk & kBusyBit)) return;
+    const uint4 rk = A.rec[k];
+    const int r = T.rule_of[s][rk.w & 0xFFu];
+    if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
+    const float bx = __uint_as_float(rk.x), by = __uint_as_float(rk.y), bz = __uint_as_float(rk.z);
     if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
     float dx = bx - x, dy = by - y, dz = bz - z;
     if (T.geometry == kBox) {
@@ -447,7 +455,9 @@ __device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Ag
     }
     const float d2 = dx * dx + dy * dy + dz * dz;
     if (!(d2 <= T.rule[r].r2)) return;
-    if (b.idx == kNone || d2 < b.d2 || (d2 == b.d2 && bid < b.id)) {
+    if (b.idx != kNone && d2 > b.d2) return;
+    const uint32_t bid = A.id[k];
+    if (b.idx == kNone || d2 < b.d2 || bid < b.id) {
         b.idx = k;
         b.id = bid;
         b.d2 = d2;
@@ -480,8 +490,8 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
     const uint32_t first = blockIdx.x * kPChunk;
     if (first >= n) return;
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
-    const uint32_t nl = compact_chunk(first, last, list, &count,
-                                      [&](uint32_t k) { return (d.sflag[k] & kClaimerBit) != 0; });
+    const uint32_t nl =
+        compact_chunk(first, last, list, &count, [&](uint32_t k) { return d.sclaim[k] != 0; });
     const Agents A = d.a[nxt];
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
@@ -492,8 +502,9 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
     const int nsub = kBlock / width;
     for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
         const uint32_t j = list[q];
-        const uint32_t s = A.sp[j];
-        const float x = A.x[j], y = A.y[j], z = A.z[j];
+        const uint4 rj = A.rec[j];
+        const uint32_t s = rj.w & 0xFFu;
+        const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
         const int comp = compartment(T, x, y, z);
         Best b{kNone, 0u, 0.0f, -1};
         if (li < ncell) {
@@ -546,6 +557,52 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
 // ---------------------------------------------------------------------------
 // finish: O7 confirmation and O8 pair products (only the claimer of a
 // confirmed pair writes, and of a mutual homotypic pair only the lower id).
+// Species are written as single bytes, so the flag byte of the same record,
+// which another thread may be testing, is never rewritten.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int nxt, int record)
+{
+    __shared__ uint32_t list[kPChunk];
+    __shared__ uint32_t count, s_holes;
+    const Tables& T = *d.tab;
+    Ctl* ctl = d.ctl;
+    const uint32_t n = ctl->n_binned;
+    const uint32_t t = ctl->t;
+    const uint32_t first = blockIdx.x * kPChunk;
+    if (first >= n) return;
+    if (threadIdx.x == 0) s_holes = 0;
+    const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
+    const uint32_t nl = compact_chunk(first, last, list, &count, [&](uint32_t k) {
+        return d.sclaim[k] && d.prop[k] != kNone;
+    });
+    const Agents A = d.a[nxt];
+    for (uint32_t q = threadIdx.x; q < nl; q += kBlock) {
+        const uint32_t j = list[q];
+        const uint32_t b = d.prop[j];
+        const uint32_t ida = A.id[j], idb = A.id[b];
+        const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
+        const unsigned long long pr = (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
+        if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) continue;
+        // b proposed too only if it carries the claimer flag (its prop is
+        // then this step's); a mutual pair fires once, from the lower id.
+        // Species are read only once this thread owns the pair.
+        if (idb < ida && (flags_of(A, b) & kMetaClaimer) && d.prop[b] == j) continue;
+        const uint32_t sj = A.rec[j].w & 0xFFu, sb = A.rec[b].w & 0xFFu;
+        const RuleDev& R = T.rule[T.rule_of[sj][sb]];
+        set_species(A, j, R.p0 < 0 ? kDead : uint32_t(R.p0));
+        set_species(A, b, R.p1 < 0 ? kDead : uint32_t(R.p1));
+        const uint32_t h = (R.p0 < 0 ? 1u : 0u) + (R.p1 < 0 ? 1u : 0u);
+        if (h) atomicAdd(&s_holes, h);
+        if (record) {
+            d.rpartner[j] = idb;
+            d.rpartner[b] = ida;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes, s_holes);
+}
+
+// ---------------------------------------------------------------------------
 // close (one workgroup): O9/O10, the step's births sorted by parent id
 // (bitonic, LDS), appended after the binned agents with ids next_id,
 // next_id + 1, ..., and the step bookkeeping.
@@ -599,11 +656,8 @@ __global__ void __launch_bounds__(kCloseThreads) k_close(Dev d, int nxt, int rec
         for (uint32_t r = threadIdx.x; r < nb; r += kCloseThreads) {
             const Birth bb = d.births[sidx[r]];
             const uint32_t j = nbin + r;
-            A.x[j] = bb.x;
-            A.y[j] = bb.y;
-            A.z[j] = bb.z;
+            A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp);
             A.id[j] = base_id + r;
-            A.sp[j] = uint8_t(bb.sp);
             if (record) {
                 d.rkey[j] = kNone;
                 d.revent[j] = kNoEvent;
@@ -614,7 +668,7 @@ __global__ void __launch_bounds__(kCloseThreads) k_close(Dev d, int nxt, int rec
     __syncthreads();
     if (threadIdx.x == 0) {
         if (err) atomicOr(&ctl->err, err);
-        const uint32_t holes = __hip_atomic_load(&ctl->holes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t holes = ctl->holes;
         ctl->agent_updates += ctl->live;
         ctl->live = nbin - holes + nb;
         ctl->holes = 0u;
@@ -625,49 +679,6 @@ __global__ void __launch_bounds__(kCloseThreads) k_close(Dev d, int nxt, int rec
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int nxt, int record)
-{
-    __shared__ uint32_t list[kPChunk];
-    __shared__ uint32_t count, s_holes;
-    const Tables& T = *d.tab;
-    Ctl* ctl = d.ctl;
-    const uint32_t n = ctl->n_binned;
-    const uint32_t t = ctl->t;
-    const uint32_t first = blockIdx.x * kPChunk;
-    if (threadIdx.x == 0) s_holes = 0;
-    if (first < n) {
-        const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
-        const uint32_t nl = compact_chunk(first, last, list, &count, [&](uint32_t k) {
-            return (d.sflag[k] & kClaimerBit) && d.prop[k] != kNone;
-        });
-        const Agents A = d.a[nxt];
-        for (uint32_t q = threadIdx.x; q < nl; q += kBlock) {
-            const uint32_t j = list[q];
-            const uint32_t b = d.prop[j];
-            const uint32_t ida = A.id[j], idb = A.id[b];
-            const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
-            const unsigned long long pr =
-                (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
-            if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) continue;
-            // b proposed too only if it carries the claimer bit (its prop is
-            // then this step's); a mutual pair fires once, from the lower
-            // id.  Species are read only once this thread owns the pair.
-            if (idb < ida && (d.sflag[b] & kClaimerBit) && d.prop[b] == j) continue;
-            const RuleDev& R = T.rule[T.rule_of[A.sp[j]][A.sp[b]]];
-            A.sp[j] = R.p0 < 0 ? kDead : uint8_t(R.p0);
-            A.sp[b] = R.p1 < 0 ? kDead : uint8_t(R.p1);
-            const uint32_t h = (R.p0 < 0 ? 1u : 0u) + (R.p1 < 0 ? 1u : 0u);
-            if (h) atomicAdd(&s_holes, h);
-            if (record) {
-                d.rpartner[j] = idb;
-                d.rpartner[b] = ida;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes, s_holes);
-}
-
 // per-species counts of live agents (LDS histogram, one atomic per species
 // per workgroup)
 __global__ void __launch_bounds__(kBlock) k_counts(Dev d, int cur)
@@ -676,9 +687,9 @@ __global__ void __launch_bounds__(kBlock) k_counts(Dev d, int cur)
     if (threadIdx.x < kMaxSpecies) h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t n = d.ctl->n_slots;
-    const uint8_t* sp = d.a[cur].sp;
+    const uint4* rec = d.a[cur].rec;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const uint32_t s = sp[i];
+        const uint32_t s = rec[i].w & 0xFFu;
         if (s < uint32_t(kMaxSpecies)) atomicAdd(&h[s], 1u);
     }
     __syncthreads();
@@ -699,6 +710,7 @@ __global__ void k_zero_counts(Dev d)
 // synchronisation and can be captured in a graph.
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
+static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
 {
@@ -724,7 +736,6 @@ void launch_scatter(const Dev& d, int cur, int record, hipStream_t s)
 {
     k_scatter<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur, record);
 }
-static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 void launch_propose(const Dev& d, int nxt, hipStream_t s)
 {
     k_propose<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, nxt);
