@@ -28,19 +28,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # per claimer (q) and per cell of the spatial hash (c) that the kernel must
 # read or write at least once for its function.  An agent is a 16-byte
 # record {x, y, z, species|flags} plus a 4-byte id.
-#   move:        reads record + id (20); writes record (16) and the
-#                (cell key, rank) pair (8)                           = 44 B/agent
-#   scan_reduce: reads the count                                     =  4 B/cell
-#   scan_down:   reads the count, writes the start, clears the count = 12 B/cell
-#   scatter:     reads (key, rank), record, id, cell start (32);
-#                writes record, id, claimer byte, claim slot (29)    = 61 B/agent
-#   propose:     claimer byte of the chunk (1 B/agent); per claimer its
-#                record and id (20) and its proposal (4)             = 1 B/agent + 24 B/claimer
-#   finish:      claimer byte of the chunk (1 B/agent); per claimer its
-#                proposal (4)                                        = 1 B/agent + 4 B/claimer
-KERNEL_BYTES = {"move": (44, 0, 0), "scan_reduce": (0, 0, 4), "scan_down": (0, 0, 12),
-                "scatter": (61, 0, 0), "propose": (1, 24, 0), "finish": (1, 4, 0),
-                "close": (0, 0, 0)}
+#   move:    reads record + id (20); writes record (16) and the (cell key,
+#            rank) pair (8)                                          = 44 B/agent
+#   scan:    reads the count, writes the start, clears the count     = 12 B/cell
+#   scatter: reads (key, rank), record, id, cell start (32); writes
+#            record, id, claimer byte, claim slot (29)               = 61 B/agent
+#   propose: claimer byte of the chunk (1 B/agent); per claimer its
+#            record and id (20) and its proposal (4)                 = 1 B/agent + 24 B/claimer
+#   finish:  claimer byte of the chunk (1 B/agent); per claimer its
+#            proposal (4)                                            = 1 B/agent + 4 B/claimer
+KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (61, 0, 0),
+                "propose": (1, 24, 0), "finish": (1, 4, 0)}
 
 
 def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:
@@ -67,7 +65,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-kernel timing region (no roofline)")
-    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each step as a captured HIP graph (default: direct launches)")
+    ap.add_argument("--cell-um", type=float, default=0.0,
+                    help="spatial-hash cell size (0: the library's choice)")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run 4 plain device copies of this many MiB (untimed), so a "
+                         "counter profile of this command holds a copy kernel of known bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -80,7 +84,14 @@ def main() -> int:
 
     model = W.c2(args.agents)
     torch.cuda.set_device(0)
-    sim = mabm.Sim(model, graphs=not args.no_graph)
+    if args.copy_calib_mb:
+        src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sim = mabm.Sim(model, graphs=args.graph, cell_um=args.cell_um)
     G, h = sim.grid()
     stream = sim.stream
     sim.step(args.warmup)
@@ -97,7 +108,7 @@ def main() -> int:
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1), sim.agent_updates() - u0
 
-    # timed region: the step as users run it (graph replay on the stream)
+    # timed region: the step as users run it
     ms, updates = timed(args.steps)
     value = updates / (ms / 1e3)
     live = updates / args.steps
@@ -130,7 +141,7 @@ def main() -> int:
         "config": {"workload": f"c2_mapk: {model.n_agents} agents, 8 species, 12 rules, "
                                f"reflecting sphere R={model.outer_radius_um:.3f} um, dt=1 us",
                    "agents": model.n_agents, "grid": G, "cell_um": round(h, 5),
-                   "graphs": not args.no_graph, "final_step": t,
+                   "graphs": args.graph, "final_step": t,
                    "live_agents_end": int(counts.sum())},
         "roofline": roof, "kernels": kernels,
         "ms_per_step_kernel_timed": None if ms_direct is None else ms_direct / args.steps,

@@ -181,7 +181,7 @@ mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uin
  * enable (1) or disable (0); read returns, per kernel of the step, the
  * number of launches timed and their total milliseconds (synchronises).
  * names receives a static string per kernel. */
-#define MABM_N_KERNELS 7
+#define MABM_N_KERNELS 5
 mabm_status mabm_profile(mabm_sim* sim, int32_t enable);
 mabm_status mabm_profile_read(mabm_sim* sim, const char** names, uint64_t* launches,
                               double* total_ms);

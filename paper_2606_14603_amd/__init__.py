@@ -28,7 +28,7 @@ ABI_VERSION = 1
 FLAG_RECORD = 1
 FLAG_NO_GRAPH = 2
 NONE32 = 0xFFFFFFFF
-N_KERNELS = 7
+N_KERNELS = 5
 
 
 class MabmError(RuntimeError):
@@ -96,7 +96,7 @@ def _ptr(a: Optional[np.ndarray]):
 
 
 def make_config(model, record: bool = False, cell_um: Optional[float] = None,
-                capacity: Optional[int] = None, graphs: bool = True) -> Config:
+                capacity: Optional[int] = None, graphs: bool = False) -> Config:
     flags = (FLAG_RECORD if record else 0) | (0 if graphs else FLAG_NO_GRAPH)
     return Config(ABI_VERSION, int(model.geometry), float(model.box_um),
                   float(model.outer_radius_um), float(model.inner_radius_um), float(model.dt_s),
@@ -113,11 +113,12 @@ def arena_bytes(model, record: bool = False, cell_um: Optional[float] = None,
 class Sim:
     """One simulation on the GPU.  ``model`` is a workloads.Model (species,
     rules, geometry, dt, seed, capacity).  By default the simulation gets its
-    own HIP stream, on which steps replay a captured graph."""
+    own HIP stream; ``graphs=True`` replays each step as a captured HIP graph
+    (measured slightly slower than direct launches on ROCm 7.2)."""
 
     def __init__(self, model, record: bool = False, cell_um: Optional[float] = None,
                  capacity: Optional[int] = None, stream=None, device: str = "cuda",
-                 arena=None, graphs: bool = True):
+                 arena=None, graphs: bool = False):
         import torch
         L = lib()
         self.n_species = len(model.species)

@@ -67,7 +67,7 @@ bool config_ok(const mabm_config* c, std::string& why)
 
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
-    size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_sum, slot,
+    size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_acc, slot,
         prop, rkey, revent, rpartner, births, counts, total;
     uint32_t ncells, ntiles;
 };
@@ -97,7 +97,7 @@ Layout make_layout(const mabm_config& c)
     const size_t padded = (size_t)L.ntiles * kScanTile;  // whole scan tiles
     L.cell_count = take(padded * 4);
     L.cell_start = take((padded + 1) * 4);
-    L.tile_sum = take((size_t)L.ntiles * 4);
+    L.tile_acc = take((size_t)2 * L.ntiles * kTileStride * 4);
     L.slot = take(cap * 8);
     L.prop = take(cap * 4);
     L.rkey = take(cap * 4);
@@ -301,7 +301,7 @@ void fill_dev(mabm_sim* s)
     d.sclaim = A + L.sclaim;
     d.cell_count = (uint32_t*)(A + L.cell_count);
     d.cell_start = (uint32_t*)(A + L.cell_start);
-    d.tile_sum = (uint32_t*)(A + L.tile_sum);
+    d.tile_acc = (uint32_t*)(A + L.tile_acc);
     d.slot = (unsigned long long*)(A + L.slot);
     d.prop = (uint32_t*)(A + L.prop);
     d.rkey = (uint32_t*)(A + L.rkey);
@@ -325,12 +325,11 @@ mabm_status finalize(mabm_sim* s, bool place)
     d.n_init = place ? s->tab.init_end[s->tab.ns - 1] : 0;
     HIP_OK(s, hipMemcpyAsync((void*)d.tab, &s->tab, sizeof(Tables), hipMemcpyHostToDevice, s->stream));
     Ctl c{};
-    c.n_slots = d.n_init;
-    c.next_id = d.n_init;
-    c.live = d.n_init;
+    c.s[0] = StepState{0u, d.n_init, d.n_init, 0u};
     HIP_OK(s, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
-    // cell counts start at zero
+    // cell counts and both parities' tile sums start at zero
     HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ntiles * kScanTile * 4, s->stream));
+    HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
     launch_fill_records(d, s->stream);
     if (place) launch_init(d, s->stream);
     HIP_OK(s, hipGetLastError());
@@ -495,20 +494,19 @@ mabm_status mabm_grid(mabm_sim* s, uint32_t* g, float* h)
 
 namespace {
 
-// one step: move, scan (2), scatter, [propose, finish], close
-void enqueue_step(mabm_sim* s, int cur)
+// one step of parity p: move, scan, scatter, [propose, finish]
+void enqueue_step(mabm_sim* s, int p)
 {
     const Dev& d = s->dev;
     const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
-    const int nxt = cur ^ 1;
     hipStream_t q = s->stream;
-    timed(s, kKMove, [&] { launch_move(d, cur, rec, q); });
-    timed(s, kKScanReduce, [&] { launch_scan_reduce(d, q); });
-    timed(s, kKScanDown, [&] { launch_scan_down(d, q); });
-    timed(s, kKScatter, [&] { launch_scatter(d, cur, rec, q); });
-    if (s->has_bimol) timed(s, kKPropose, [&] { launch_propose(d, nxt, q); });
-    if (s->has_bimol) timed(s, kKFinish, [&] { launch_finish(d, nxt, rec, q); });
-    timed(s, kKClose, [&] { launch_close(d, nxt, rec, q); });
+    timed(s, kKMove, [&] { launch_move(d, p, rec, q); });
+    timed(s, kKScan, [&] { launch_scan(d, p, q); });
+    timed(s, kKScatter, [&] { launch_scatter(d, p, rec, q); });
+    if (s->has_bimol) {
+        timed(s, kKPropose, [&] { launch_propose(d, p, q); });
+        timed(s, kKFinish, [&] { launch_finish(d, p, rec, q); });
+    }
 }
 
 // capture one step of each parity as a graph on the caller's stream
@@ -564,7 +562,7 @@ mabm_status mabm_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t
     st = live_counts(s, c, &ctl);
     if (st != MABM_OK) return st;
     for (uint32_t k = 0; k < n_species; ++k) out[k] = k < (uint32_t)kMaxSpecies ? c[k] : 0;
-    if (out_step) *out_step = ctl.t;
+    if (out_step) *out_step = ctl.s[s->parity].t;
     return MABM_OK;
 }
 
@@ -579,7 +577,7 @@ mabm_status mabm_size(mabm_sim* s, uint32_t* n_live, uint32_t* next_id)
     st = live_counts(s, c, &ctl);
     if (st != MABM_OK) return st;
     if (n_live) *n_live = (uint32_t)std::accumulate(c.begin(), c.end(), 0ull);
-    if (next_id) *next_id = ctl.next_id;
+    if (next_id) *next_id = ctl.s[s->parity].next_id;
     return MABM_OK;
 }
 
@@ -593,7 +591,7 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
     Ctl ctl{};
     st = sync_ctl(s, &ctl);
     if (st != MABM_OK) return st;
-    const uint32_t n = ctl.n_slots;
+    const uint32_t n = ctl.s[s->parity].n_slots;
     const Agents& A = s->dev.a[s->parity];
     std::vector<uint4> hr(n);
     std::vector<uint32_t> hid(n), hk(n), hp(n);
@@ -665,10 +663,7 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
         HIP_OK(s, hipMemcpyAsync(A.id, id, n * 4, hipMemcpyHostToDevice, s->stream));
     }
     Ctl ctl{};
-    ctl.t = t;
-    ctl.n_slots = n;
-    ctl.next_id = next_id;
-    ctl.live = n;
+    ctl.s[0] = StepState{t, n, next_id, 0u};
     HIP_OK(s, hipMemcpyAsync(s->dev.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;

@@ -22,7 +22,8 @@ constexpr uint32_t kMetaClaimer = 1u << 9;  // non-busy agent of a claiming spec
 constexpr int kMetaSpeciesByte = 12;        // byte offset of the species in a record
 constexpr int kMetaFlagsByte = 13;          // byte offset of the flags in a record
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kMaxBirthsPerStep = 4096;  // births sorted by one workgroup
+constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
+constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
 constexpr int kScanItems = 8;                 // cells per thread in the scan
 constexpr int kScanThreads = 256;
 constexpr int kScanTile = kScanItems * kScanThreads;
@@ -65,16 +66,23 @@ struct Tables {
     RuleDev rule[kMaxRules];
 };
 
-struct Ctl {
-    uint32_t t;            // step counter
-    uint32_t n_slots;      // entries of the current agent arrays (holes included)
-    uint32_t n_binned;     // agents binned this step
-    uint32_t n_births;     // birth records appended this step
+// Step scalars are double-buffered by parity p = t mod 2 (the buffer the
+// step starts from): the kernels of a step read side p, and the step's last
+// bookkeeping writes side p ^ 1 for the next step, so no kernel of a step
+// ever sees the next step's values.
+struct StepState {
+    uint32_t t;        // step counter
+    uint32_t n_slots;  // entries of the agent arrays (holes included)
     uint32_t next_id;
+    uint32_t pad;
+};
+
+struct Ctl {
+    StepState s[2];
+    uint32_t n_births[2];  // birth records appended by the step of parity p
+    uint32_t holes[2];     // agents consumed by pair rules in the step of parity p
+    uint32_t n_binned;     // agents binned in the current step
     uint32_t err;          // ErrBit, sticky
-    uint32_t live;         // live agents in the current arrays
-    uint32_t holes;        // agents consumed by pair rules this step
-    uint32_t pad[4];
     unsigned long long agent_updates;  // sum of live agents at step starts
 };
 
@@ -97,7 +105,8 @@ struct Dev {
     uint8_t* sclaim;      // per sorted agent: 1 = claimer this step
     uint32_t* cell_count;  // ncells rounded up to whole scan tiles
     uint32_t* cell_start;  // padded ncells + 1
-    uint32_t* tile_sum;    // per scan tile
+    uint32_t* tile_acc;    // [2][ntiles * kTileStride]: cell-count sums per scan tile,
+                           // accumulated by move, one set per parity
     unsigned long long* slot;
     uint32_t* prop;        // per sorted agent: proposed partner index
     uint32_t* rkey;        // record arrays, indexed like the current agents
@@ -109,19 +118,17 @@ struct Dev {
 };
 
 // kernel indices for per-kernel timing
-enum KernelId { kKMove = 0, kKScanReduce, kKScanDown, kKScatter, kKPropose, kKFinish, kKClose,
-                kNumKernels };
+enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 // launch entry points (kernels.hip); each enqueues one kernel on `s`
 void launch_init(const Dev& d, hipStream_t s);
-void launch_move(const Dev& d, int cur, int record, hipStream_t s);
-void launch_scan_reduce(const Dev& d, hipStream_t s);
-void launch_scan_down(const Dev& d, hipStream_t s);
-void launch_scatter(const Dev& d, int cur, int record, hipStream_t s);
-void launch_propose(const Dev& d, int nxt, hipStream_t s);
-void launch_finish(const Dev& d, int nxt, int record, hipStream_t s);
-void launch_close(const Dev& d, int nxt, int record, hipStream_t s);
+// p: parity of the step (its agents start in a[p] and are sorted into a[p ^ 1])
+void launch_move(const Dev& d, int p, int record, hipStream_t s);
+void launch_scan(const Dev& d, int p, hipStream_t s);
+void launch_scatter(const Dev& d, int p, int record, hipStream_t s);
+void launch_propose(const Dev& d, int p, hipStream_t s);
+void launch_finish(const Dev& d, int p, int record, hipStream_t s);
 void launch_counts(const Dev& d, int cur, hipStream_t s);
 void launch_fill_records(const Dev& d, hipStream_t s);
 

@@ -1,40 +1,39 @@
 // kernels.hip -- the per-step kernels of the molecule-agent update for
-// gfx950 (wave64).  One step (O2..O10 of the step definition) is seven
+// gfx950 (wave64).  One step (O2..O10 of the step definition) of parity p
+// (agents start in buffer p and are sorted into buffer p ^ 1) is five
 // launches:
 //
-//   move         one Philox block per agent gives the event draw and the
-//                Brownian step; boundaries, event effects, birth records;
-//                the cell key of the moved position and its rank in the
-//                cell, by one atomic per run of equal keys in a wave (agents
-//                arrive sorted by cell from the previous step, so runs are
-//                long and the atomics spread over many cells)
-//   scan_reduce  per-tile sums of the cell counts
-//   scan_down    each tile adds the sums of the tiles before it, scans its
-//                counts into cell starts and clears them for the next step
-//   scatter      agents to cell order in the other buffer (holes and
-//                degraded agents dropped: stream compaction)
-//   propose      per workgroup, a chunk of 512 sorted agents: its claimers
-//                are compacted in LDS, then each is searched by a subgroup
-//                of lanes, one stencil cell per lane, for the nearest
-//                eligible partner; Bernoulli draw; handshake keys into both
-//                claim slots
-//   finish       per chunk: confirmation and pair products
-//   close        one workgroup: the step's births sorted by parent id and
-//                appended with fresh ids; the step bookkeeping
+//   move     one Philox block per agent gives the event draw and the
+//            Brownian step; boundaries, event effects, birth records; the
+//            cell key of the moved position and its rank in the cell, by one
+//            atomic per run of equal keys in a wave (agents arrive sorted by
+//            cell from the previous step, so runs are long and the atomics
+//            spread over many cells), and the per-tile sums of the counts
+//            the same way
+//   scan     each tile of 2048 cells adds the sums of the tiles before it,
+//            scans its counts into cell starts and clears them
+//   scatter  agents to cell order in the other buffer (holes and degraded
+//            agents dropped: stream compaction); one extra workgroup ranks
+//            the step's births by parent id, appends them with fresh ids and
+//            writes the next step's scalars
+//   propose  per workgroup, a chunk of 512 sorted agents: its claimers are
+//            compacted in LDS, then each is searched by a subgroup of lanes,
+//            one stencil cell per lane, for the nearest eligible partner;
+//            Bernoulli draw; handshake keys into both claim slots
+//   finish   per chunk: confirmation and pair products
 //
 // An agent is a 16-byte record {x, y, z, meta} plus a 4-byte id, so a
 // streaming kernel moves whole records with 16-byte accesses and a candidate
 // check in the neighbour search is one 16-byte gather.  No kernel spins or
 // waits on another workgroup, and no hot loop puts many atomics on one
-// address (they serialise at the memory side).  Nothing here is a dense
-// contraction.
+// address or one 4 KiB page (they serialise at the memory side).  Nothing
+// here is a dense contraction.
 #include "device_math.hpp"
 #include "engine.hpp"
 
 namespace mabm {
 
-const char* const kKernelNames[kNumKernels] = {"move",    "scan_reduce", "scan_down", "scatter",
-                                               "propose", "finish",      "close"};
+const char* const kKernelNames[kNumKernels] = {"move", "scan", "scatter", "propose", "finish"};
 
 namespace {
 
@@ -45,6 +44,45 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // lanes strictly below this one
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b % 8), and each XCD has its own L2.  This renumbering gives every XCD a
+// contiguous run of chunks, so chunks that gather from the same neighbouring
+// cells share one L2.  It is a bijection of [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_chunk()
+{
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+// Lanes whose key equals the previous lane's form a run; each run head adds
+// the run length to counter[key * stride] with one atomic.  Returns the
+// counter's old value plus the lane's offset in its run.  A key split over
+// several runs gets several disjoint ranges, so any lane order is correct;
+// sorted keys make runs long and atomics few.  kNone lanes take no part.
+__device__ __forceinline__ uint32_t run_add(uint32_t key, uint32_t* counter, uint32_t stride)
+{
+    const int lane = lane_id();
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || key != prev;
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int head_lane = 63 - __builtin_clzll(heads & upto);
+    const uint64_t after = heads & ~upto;
+    const int next_head = after ? __builtin_ctzll(after) : 64;
+    uint32_t base = 0;
+    if (head && key != kNone)
+        base = atomicAdd(&counter[size_t(key) * stride], uint32_t(next_head - lane));
+    base = __shfl(base, head_lane, 64);
+    return base + uint32_t(lane - head_lane);
+}
+
+__device__ __forceinline__ uint32_t* tile_acc(const Dev& d, int p)
+{
+    return d.tile_acc + size_t(p) * d.ntiles * kTileStride;
+}
 
 __device__ __forceinline__ uint4 make_rec(float x, float y, float z, uint32_t meta)
 {
@@ -147,10 +185,10 @@ __device__ void release_offset(const Tables& T, const RuleDev& R, uint32_t id, u
     ux = uy = uz = 0.0f;
 }
 
-__device__ __forceinline__ void push_birth(const Dev& d, uint32_t parent, int sp, float x, float y,
-                                           float z)
+__device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent, int sp, float x,
+                                           float y, float z)
 {
-    const uint32_t k = atomicAdd(&d.ctl->n_births, 1u);
+    const uint32_t k = atomicAdd(&d.ctl->n_births[p], 1u);
     if (k < kMaxBirthsPerStep) d.births[k] = Birth{parent, uint32_t(sp), x, y, z};
 }
 
@@ -159,14 +197,13 @@ __device__ __forceinline__ void push_birth(const Dev& d, uint32_t parent, int sp
 // unimolecular part of O8, then the cell key of the moved position and the
 // agent's rank within its cell.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
+__global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
 {
     const Tables& T = *d.tab;
-    Ctl* ctl = d.ctl;
-    const uint32_t n = ctl->n_slots;
-    const uint32_t t = ctl->t;
+    const uint32_t n = d.ctl->s[p].n_slots;
+    const uint32_t t = d.ctl->s[p].t;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const Agents A = d.a[cur];
+    const Agents A = d.a[p];
     uint32_t key = kNone;
     uint4 r = {0u, 0u, 0u, kDead};
     uint32_t id = 0;
@@ -251,7 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
                     cy = wrap_box(T, cy);
                     cz = wrap_box(T, cz);
                 }
-                push_birth(d, id, R.p1, cx, cy, cz);
+                push_birth(d, p, id, R.p1, cx, cy, cz);
                 break;
             }
             default: {  // kEmit
@@ -263,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
                     cy = wrap_box(T, cy);
                     cz = wrap_box(T, cz);
                 }
-                push_birth(d, id, R.p1, cx, cy, cz);
+                push_birth(d, p, id, R.p1, cx, cy, cz);
                 break;
             }
             }
@@ -274,28 +311,17 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int cur, int record)
             if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
         }
     }
-    // Rank within the cell: lanes with equal keys form runs (the input is
-    // cell-sorted); the head of each run adds the run length atomically and
-    // the run's lanes take consecutive ranks.  A key split over several
-    // runs gets several disjoint ranges, so any input order is correct.
-    const int lane = lane_id();
-    const uint32_t prev = __shfl_up(key, 1, 64);
-    const bool head = lane == 0 || key != prev;
-    const uint64_t heads = __ballot(head);
-    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const int head_lane = 63 - __builtin_clzll(heads & upto);
-    const uint64_t after = heads & ~upto;
-    const int next_head = after ? __builtin_ctzll(after) : 64;
-    uint32_t base = 0;
-    if (head && key != kNone) base = atomicAdd(&d.cell_count[key], uint32_t(next_head - lane));
-    base = __shfl(base, head_lane, 64);
-    if (i < n) d.kr[i] = uint2{key, base + uint32_t(lane - head_lane)};
+    // rank within the cell, and the per-tile sums the scan starts from
+    const uint32_t rank = run_add(key, d.cell_count, 1u);
+    run_add(key == kNone ? kNone : key / uint32_t(kScanTile), tile_acc(d, p), kTileStride);
+    if (i < n) d.kr[i] = uint2{key, rank};
 }
 
 // ---------------------------------------------------------------------------
-// scan of the cell counts in two launches, neither of which waits on another
-// workgroup: per-tile sums, then per tile the sum of the earlier tiles'
-// sums, the exclusive scan of its 2048 counts and the clearing of the counts.
+// scan of the cell counts, one launch, no waiting between workgroups: each
+// tile sums the earlier tiles' totals (accumulated by move), scans its 2048
+// counts into cell starts, clears them, and clears its accumulator of the
+// other parity for the next step.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 {
@@ -327,21 +353,12 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
     return off + inc - v;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(Dev d)
-{
-    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    const uint4* cnt4 = reinterpret_cast<const uint4*>(d.cell_count + base);
-    const uint4 a = cnt4[0], b = cnt4[1];
-    uint32_t total;
-    block_excl_scan(a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w, &total);
-    if (threadIdx.x == 0) d.tile_sum[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(Dev d)
+__global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 {
     const uint32_t tile = blockIdx.x;
+    const uint32_t* acc = tile_acc(d, p);
     uint32_t before = 0;
-    for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += d.tile_sum[k];
+    for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += acc[size_t(k) * kTileStride];
     uint32_t prefix;
     block_excl_scan(before, &prefix);
     const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
@@ -364,9 +381,68 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(Dev d)
     st4[1] = uint4{out[4], out[5], out[6], out[7]};
     cnt4[0] = uint4{0u, 0u, 0u, 0u};
     cnt4[1] = uint4{0u, 0u, 0u, 0u};
-    if (tile == d.ntiles - 1 && threadIdx.x == 0) {
-        d.cell_start[d.ntiles * kScanTile] = prefix + total;
-        d.ctl->n_binned = prefix + total;
+    if (threadIdx.x == 0) {
+        tile_acc(d, p ^ 1)[size_t(tile) * kTileStride] = 0u;
+        if (tile == d.ntiles - 1) {
+            d.cell_start[d.ntiles * kScanTile] = prefix + total;
+            d.ctl->n_binned = prefix + total;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// births and bookkeeping (O9, O10), run by the extra last workgroup of the
+// scatter launch: child r of the step, ranked by parent id among the step's
+// births (ranks by counting: parent ids are distinct, as a parent has at most
+// one child per step), goes to slot n_binned + r with id next_id + r; then
+// the next step's scalars.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRankLds = 1024;  // births ranked from LDS; more read from L2
+
+__device__ void births_and_bookkeeping(const Dev& d, int p, int record)
+{
+    __shared__ uint32_t skey[kRankLds];
+    Ctl* ctl = d.ctl;
+    const StepState cur = ctl->s[p];
+    const uint32_t nbin = ctl->n_binned;
+    uint32_t nb = ctl->n_births[p];
+    uint32_t err = 0;
+    if (nb > kMaxBirthsPerStep) {
+        err = kErrBirths;
+        nb = 0;
+    } else if (uint64_t(nbin) + nb > d.capacity) {
+        err = kErrCapacity;
+        nb = 0;
+    }
+    const bool in_lds = nb <= kRankLds;
+    if (in_lds)
+        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) skey[k] = d.births[k].parent;
+    __syncthreads();
+    const Agents A = d.a[p ^ 1];
+    for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
+        const Birth bb = d.births[k];
+        uint32_t r = 0;
+        if (in_lds)
+            for (uint32_t m = 0; m < nb; ++m) r += skey[m] < bb.parent ? 1u : 0u;
+        else
+            for (uint32_t m = 0; m < nb; ++m) r += d.births[m].parent < bb.parent ? 1u : 0u;
+        const uint32_t j = nbin + r;
+        A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp);
+        A.id[j] = cur.next_id + r;
+        if (record) {
+            d.rkey[j] = kNone;
+            d.revent[j] = kNoEvent;
+            d.rpartner[j] = kNone;
+        }
+    }
+    if (threadIdx.x == 0) {
+        if (err) atomicOr(&ctl->err, err);
+        // live agents at this step's start: its slots minus the holes the
+        // previous step's pair rules left in them
+        ctl->agent_updates += cur.n_slots - ctl->holes[p ^ 1];
+        ctl->holes[p ^ 1] = 0u;
+        ctl->n_births[p ^ 1] = 0u;
+        ctl->s[p ^ 1] = StepState{cur.t + 1u, nbin + nb, cur.next_id + nb, 0u};
     }
 }
 
@@ -375,17 +451,21 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(Dev d)
 // (non-busy agent of a claiming species) is set in the record and in the
 // one-byte array the propose/finish chunks scan.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int cur, int record)
+__global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 {
+    if (blockIdx.x == gridDim.x - 1) {
+        births_and_bookkeeping(d, p, record);
+        return;
+    }
     const Tables& T = *d.tab;
-    const uint32_t n = d.ctl->n_slots;
+    const uint32_t n = d.ctl->s[p].n_slots;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const uint2 kr = d.kr[i];
     if (kr.x == kNone) return;
     const uint32_t j = d.cell_start[kr.x] + kr.y;
-    const Agents A = d.a[cur];
-    const Agents B = d.a[cur ^ 1];
+    const Agents A = d.a[p];
+    const Agents B = d.a[p ^ 1];
     uint4 r = A.rec[i];
     const bool claim = !(r.w & kMetaBusy) && T.claimer[r.w & 0xFFu];
     if (claim) r.w |= kMetaClaimer;
@@ -480,19 +560,19 @@ __device__ __forceinline__ void reduce_best(Best& b, int width)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
+__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t count;
     const Tables& T = *d.tab;
     const uint32_t n = d.ctl->n_binned;
-    const uint32_t t = d.ctl->t;
-    const uint32_t first = blockIdx.x * kPChunk;
+    const uint32_t t = d.ctl->s[p].t;
+    const uint32_t first = xcd_chunk() * kPChunk;
     if (first >= n) return;
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const uint32_t nl =
         compact_chunk(first, last, list, &count, [&](uint32_t k) { return d.sclaim[k] != 0; });
-    const Agents A = d.a[nxt];
+    const Agents A = d.a[p ^ 1];
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
     // a subgroup of `width` lanes per claimer, one stencil cell per lane
@@ -560,22 +640,22 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int nxt)
 // Species are written as single bytes, so the flag byte of the same record,
 // which another thread may be testing, is never rewritten.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int nxt, int record)
+__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t count, s_holes;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
     const uint32_t n = ctl->n_binned;
-    const uint32_t t = ctl->t;
-    const uint32_t first = blockIdx.x * kPChunk;
+    const uint32_t t = ctl->s[p].t;
+    const uint32_t first = xcd_chunk() * kPChunk;
     if (first >= n) return;
     if (threadIdx.x == 0) s_holes = 0;
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const uint32_t nl = compact_chunk(first, last, list, &count, [&](uint32_t k) {
         return d.sclaim[k] && d.prop[k] != kNone;
     });
-    const Agents A = d.a[nxt];
+    const Agents A = d.a[p ^ 1];
     for (uint32_t q = threadIdx.x; q < nl; q += kBlock) {
         const uint32_t j = list[q];
         const uint32_t b = d.prop[j];
@@ -599,84 +679,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int nxt, int record)
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes, s_holes);
-}
-
-// ---------------------------------------------------------------------------
-// close (one workgroup): O9/O10, the step's births sorted by parent id
-// (bitonic, LDS), appended after the binned agents with ids next_id,
-// next_id + 1, ..., and the step bookkeeping.
-// ---------------------------------------------------------------------------
-constexpr int kCloseThreads = 1024;
-
-__global__ void __launch_bounds__(kCloseThreads) k_close(Dev d, int nxt, int record)
-{
-    __shared__ uint32_t skey[kMaxBirthsPerStep];
-    __shared__ uint32_t sidx[kMaxBirthsPerStep];
-    Ctl* ctl = d.ctl;
-    const uint32_t nbin = ctl->n_binned;
-    uint32_t nb = ctl->n_births;
-    uint32_t err = 0;
-    if (nb > kMaxBirthsPerStep) {
-        err = kErrBirths;
-        nb = 0;
-    } else if (uint64_t(nbin) + nb > d.capacity) {
-        err = kErrCapacity;
-        nb = 0;
-    }
-    if (nb > 0) {
-        uint32_t np = 1;
-        while (np < nb) np <<= 1;
-        for (uint32_t k = threadIdx.x; k < np; k += kCloseThreads) {
-            skey[k] = k < nb ? d.births[k].parent : 0xFFFFFFFFu;
-            sidx[k] = k;
-        }
-        __syncthreads();
-        for (uint32_t size = 2; size <= np; size <<= 1) {
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t k = threadIdx.x; k < np; k += kCloseThreads) {
-                    const uint32_t o = k ^ stride;
-                    if (o > k) {
-                        const bool up = (k & size) == 0;
-                        const uint32_t a = skey[k], b = skey[o];
-                        if ((a > b) == up) {
-                            skey[k] = b;
-                            skey[o] = a;
-                            const uint32_t ti = sidx[k];
-                            sidx[k] = sidx[o];
-                            sidx[o] = ti;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        const Agents A = d.a[nxt];
-        const uint32_t base_id = ctl->next_id;
-        for (uint32_t r = threadIdx.x; r < nb; r += kCloseThreads) {
-            const Birth bb = d.births[sidx[r]];
-            const uint32_t j = nbin + r;
-            A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp);
-            A.id[j] = base_id + r;
-            if (record) {
-                d.rkey[j] = kNone;
-                d.revent[j] = kNoEvent;
-                d.rpartner[j] = kNone;
-            }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (err) atomicOr(&ctl->err, err);
-        const uint32_t holes = ctl->holes;
-        ctl->agent_updates += ctl->live;
-        ctl->live = nbin - holes + nb;
-        ctl->holes = 0u;
-        ctl->n_slots = nbin + nb;
-        ctl->next_id += nb;
-        ctl->n_births = 0u;
-        ctl->t += 1u;
-    }
+    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes[p], s_holes);
 }
 
 // per-species counts of live agents (LDS histogram, one atomic per species
@@ -686,7 +689,7 @@ __global__ void __launch_bounds__(kBlock) k_counts(Dev d, int cur)
     __shared__ uint32_t h[kMaxSpecies];
     if (threadIdx.x < kMaxSpecies) h[threadIdx.x] = 0;
     __syncthreads();
-    const uint32_t n = d.ctl->n_slots;
+    const uint32_t n = d.ctl->s[cur].n_slots;
     const uint4* rec = d.a[cur].rec;
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const uint32_t s = rec[i].w & 0xFFu;
@@ -720,33 +723,23 @@ void launch_fill_records(const Dev& d, hipStream_t s)
 {
     k_fill_records<<<blocks_for(d.capacity), kBlock, 0, s>>>(d);
 }
-void launch_move(const Dev& d, int cur, int record, hipStream_t s)
+void launch_move(const Dev& d, int p, int record, hipStream_t s)
 {
-    k_move<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur, record);
+    k_move<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, p, record);
 }
-void launch_scan_reduce(const Dev& d, hipStream_t s)
+void launch_scan(const Dev& d, int p, hipStream_t s) { k_scan<<<d.ntiles, kScanThreads, 0, s>>>(d, p); }
+void launch_scatter(const Dev& d, int p, int record, hipStream_t s)
 {
-    k_scan_reduce<<<d.ntiles, kScanThreads, 0, s>>>(d);
+    // one workgroup per 256 slots, plus the births/bookkeeping workgroup
+    k_scatter<<<blocks_for(d.capacity) + 1, kBlock, 0, s>>>(d, p, record);
 }
-void launch_scan_down(const Dev& d, hipStream_t s)
+void launch_propose(const Dev& d, int p, hipStream_t s)
 {
-    k_scan_down<<<d.ntiles, kScanThreads, 0, s>>>(d);
+    k_propose<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, p);
 }
-void launch_scatter(const Dev& d, int cur, int record, hipStream_t s)
+void launch_finish(const Dev& d, int p, int record, hipStream_t s)
 {
-    k_scatter<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur, record);
-}
-void launch_propose(const Dev& d, int nxt, hipStream_t s)
-{
-    k_propose<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, nxt);
-}
-void launch_finish(const Dev& d, int nxt, int record, hipStream_t s)
-{
-    k_finish<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, nxt, record);
-}
-void launch_close(const Dev& d, int nxt, int record, hipStream_t s)
-{
-    k_close<<<1, kCloseThreads, 0, s>>>(d, nxt, record);
+    k_finish<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, p, record);
 }
 void launch_counts(const Dev& d, int cur, hipStream_t s)
 {
