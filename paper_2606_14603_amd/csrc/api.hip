@@ -36,15 +36,26 @@ float extent_of(const mabm_config& c)
     return c.geometry == MABM_PERIODIC_BOX ? c.box_um : c.outer_radius_um * 2.0f;
 }
 
+constexpr uint32_t kMaxGrid = 512;  // cells per axis
+
 // cells per axis implied by the configuration alone: the requested cell
-// size, or about one cell per agent of capacity over the bounding box
+// size, or the power of two nearest (in log) to one cell per agent of
+// capacity over the bounding box
 uint32_t grid_from_config(const mabm_config& c)
 {
     const double ext = extent_of(c);
     double g;
     if (c.cell_um > 0.0f) g = std::floor(ext / (double)c.cell_um);
-    else g = std::round(std::cbrt((double)c.capacity));
-    return (uint32_t)std::min(1024.0, std::max(3.0, g));
+    else g = std::exp2(std::round(std::log2(std::cbrt((double)c.capacity))));
+    return (uint32_t)std::min((double)kMaxGrid, std::max(3.0, g));
+}
+
+// bits per axis of the Morton sort key for G cells per axis
+uint32_t morton_bits(uint32_t g)
+{
+    uint32_t b = 0;
+    while ((1u << b) < g) ++b;
+    return b;
 }
 
 bool config_ok(const mabm_config* c, std::string& why)
@@ -82,8 +93,8 @@ Layout make_layout(const mabm_config& c)
         return o;
     };
     const size_t cap = c.capacity;
-    const uint32_t g = grid_from_config(c);
-    L.ncells = g * g * g;
+    const uint32_t b = morton_bits(grid_from_config(c));
+    L.ncells = 1u << (3 * b);
     L.ntiles = (L.ncells + kScanTile - 1) / kScanTile;
     L.ctl = take(sizeof(Ctl));
     L.tab = take(sizeof(Tables));
@@ -279,6 +290,7 @@ mabm_status build_tables(mabm_sim* s)
     s->G = G;
     s->h = (float)(ext / G);
     T.G = G;
+    T.morton_bits = morton_bits(G);
     T.lo = c.geometry == MABM_PERIODIC_BOX ? 0.0f : -c.outer_radius_um;
     T.inv_h = (float)((double)G / ext);
     T.stencil8 = (rmax > 0.0 && ext / G >= 2.02 * rmax) ? 1u : 0u;
@@ -320,7 +332,7 @@ mabm_status finalize(mabm_sim* s, bool place)
     mabm_status st = build_tables(s);
     if (st != MABM_OK) return st;
     Dev& d = s->dev;
-    d.ncells = s->G * s->G * s->G;
+    d.ncells = 1u << (3 * s->tab.morton_bits);
     d.ntiles = (d.ncells + kScanTile - 1) / kScanTile;
     d.n_init = place ? s->tab.init_end[s->tab.ns - 1] : 0;
     HIP_OK(s, hipMemcpyAsync((void*)d.tab, &s->tab, sizeof(Tables), hipMemcpyHostToDevice, s->stream));

@@ -169,9 +169,44 @@ __device__ __forceinline__ uint32_t cell_coord(const Tables& T, float v)
     return uint32_t(f);
 }
 
+// Morton (Z-order) index: the bits of the three 10-bit cell coordinates
+// interleaved (x lowest).  Cells adjacent in space are close in this order at
+// every scale, which keeps the neighbour search's gathers local.
+__device__ __forceinline__ uint32_t spread_bits3(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t gather_bits3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0x030000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t cell_key(uint32_t cx, uint32_t cy, uint32_t cz)
+{
+    return spread_bits3(cx) | (spread_bits3(cy) << 1) | (spread_bits3(cz) << 2);
+}
+
+// sort key of the cell holding a position
 __device__ __forceinline__ uint32_t cell_of(const Tables& T, float x, float y, float z)
 {
-    return cell_coord(T, x) + T.G * (cell_coord(T, y) + T.G * cell_coord(T, z));
+    return cell_key(cell_coord(T, x), cell_coord(T, y), cell_coord(T, z));
+}
+
+// the exported cell id cx + G (cy + G cz) of a sort key
+__device__ __forceinline__ uint32_t linear_cell(const Tables& T, uint32_t key)
+{
+    return gather_bits3(key) + T.G * (gather_bits3(key >> 1) + T.G * gather_bits3(key >> 2));
 }
 
 }  // namespace mabm

@@ -53,6 +53,8 @@ struct Tables {
     float L, halfL, Rout, Rout2, Rin, Rin2;
     float lo, inv_h;
     uint32_t G, stencil8;  // cells per axis; 1 = 8-cell stencil (h >= 2 R_max)
+    uint32_t morton_bits;  // cells are sorted by the Morton (Z-order) index of their
+                           // coordinates over a 2^bits grid per axis
     uint32_t key0, key1;   // Philox key (seed low, high)
     uint32_t has_births, pad;
     uint32_t init_end[kMaxSpecies];  // prefix sums of initial counts (placement)

@@ -22,7 +22,9 @@
 //            Bernoulli draw; handshake keys into both claim slots
 //   finish   per chunk: confirmation and pair products
 //
-// An agent is a 16-byte record {x, y, z, meta} plus a 4-byte id, so a
+// Cells are sorted by the Morton index of their coordinates, so the cells of
+// a neighbourhood are close in memory.  An agent is a 16-byte record
+// {x, y, z, meta} plus a 4-byte id, so a
 // streaming kernel moves whole records with 16-byte accesses and a candidate
 // check in the neighbour search is one 16-byte gather.  No kernel spins or
 // waits on another workgroup, and no hot loop puts many atomics on one
@@ -362,25 +364,32 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
     uint32_t prefix;
     block_excl_scan(before, &prefix);
     const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+    constexpr int kVec = kScanItems / 4;
     uint4* cnt4 = reinterpret_cast<uint4*>(d.cell_count + base);
-    const uint4 a = cnt4[0], b = cnt4[1];
-    const uint32_t v[kScanItems] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint4 v[kVec];
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) sum += v[k];
+    for (int k = 0; k < kVec; ++k) {
+        v[k] = cnt4[k];
+        sum += v[k].x + v[k].y + v[k].z + v[k].w;
+    }
     uint32_t total;
     uint32_t run = prefix + block_excl_scan(sum, &total);
-    uint32_t out[kScanItems];
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        out[k] = run;
-        run += v[k];
-    }
     uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + base);
-    st4[0] = uint4{out[0], out[1], out[2], out[3]};
-    st4[1] = uint4{out[4], out[5], out[6], out[7]};
-    cnt4[0] = uint4{0u, 0u, 0u, 0u};
-    cnt4[1] = uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) {
+        uint4 o;
+        o.x = run;
+        run += v[k].x;
+        o.y = run;
+        run += v[k].y;
+        o.z = run;
+        run += v[k].z;
+        o.w = run;
+        run += v[k].w;
+        st4[k] = o;
+        cnt4[k] = uint4{0u, 0u, 0u, 0u};
+    }
     if (threadIdx.x == 0) {
         tile_acc(d, p ^ 1)[size_t(tile) * kTileStride] = 0u;
         if (tile == d.ntiles - 1) {
@@ -474,31 +483,42 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     d.sclaim[j] = claim ? 1 : 0;
     d.slot[j] = ~0ull;
     if (record) {
-        d.rkey[j] = kr.x;
+        d.rkey[j] = linear_cell(T, kr.x);
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
     }
 }
 
 // Compact, in LDS, the agents of this workgroup's chunk [first, last) that
-// satisfy `pred` (one LDS atomic per wave).  Returns the list length.
+// satisfy `pred` (at most kPChunk = 2 x kBlock agents).  Each thread tests
+// its two agents before any list write, so the loads they need are in
+// flight together; one LDS atomic per wave reserves the list space.
+// Returns the list length.
 template <class Pred>
 __device__ __forceinline__ uint32_t compact_chunk(uint32_t first, uint32_t last, uint32_t* list,
                                                   uint32_t* count, Pred pred)
 {
+    static_assert(kPChunk == 2 * kBlock, "two agents per thread");
     if (threadIdx.x == 0) *count = 0;
     __syncthreads();
-    for (uint32_t k = first + threadIdx.x; k < last; k += kBlock) {
-        const bool c = pred(k);
-        const uint64_t m = __ballot(c);
-        if (m) {
-            const int leader = __builtin_ctzll(m);
-            uint32_t base = 0;
-            if (lane_id() == leader) base = atomicAdd(count, uint32_t(__builtin_popcountll(m)));
-            base = __shfl(base, leader, 64);
-            if (c) list[base + __builtin_popcountll(m & lanes_below())] = k;
-        }
+    const uint32_t k0 = first + 2u * threadIdx.x, k1 = k0 + 1u;
+    const bool c0 = k0 < last && pred(k0);
+    const bool c1 = k1 < last && pred(k1);
+    const uint32_t mine = (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
+    // wave-level exclusive prefix of the per-thread counts
+    uint32_t incl = mine;
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
     }
+    const uint32_t wave_total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (lane == 0 && wave_total) base = atomicAdd(count, wave_total);
+    base = __shfl(base, 0, 64) + incl - mine;
+    if (c0) list[base++] = k0;
+    if (c1) list[base] = k1;
     __syncthreads();
     return *count;
 }
@@ -519,10 +539,9 @@ struct Best {
 };
 
 __device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Agents& A,
-                                         uint32_t k, uint32_t self, uint32_t s, float x,
-                                         float y, float z, int comp, Best& b)
+                                         const uint4& rk, uint32_t k, uint32_t self, uint32_t s,
+                                         float x, float y, float z, int comp, Best& b)
 {
-    const uint4 rk = A.rec[k];
     const int r = T.rule_of[s][rk.w & 0xFFu];
     if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
     const float bx = __uint_as_float(rk.x), by = __uint_as_float(rk.y), bz = __uint_as_float(rk.z);
@@ -563,6 +582,7 @@ __device__ __forceinline__ void reduce_best(Best& b, int width)
 __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 {
     __shared__ uint32_t list[kPChunk];
+    __shared__ uint4 lrec[kPChunk];
     __shared__ uint32_t count;
     const Tables& T = *d.tab;
     const uint32_t n = d.ctl->n_binned;
@@ -570,9 +590,12 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     const uint32_t first = xcd_chunk() * kPChunk;
     if (first >= n) return;
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
+    const Agents A = d.a[p ^ 1];
+    // the chunk's claimers, then their records, compacted into LDS
     const uint32_t nl =
         compact_chunk(first, last, list, &count, [&](uint32_t k) { return d.sclaim[k] != 0; });
-    const Agents A = d.a[p ^ 1];
+    for (uint32_t q = threadIdx.x; q < nl; q += kBlock) lrec[q] = A.rec[list[q]];
+    __syncthreads();
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
     // a subgroup of `width` lanes per claimer, one stencil cell per lane
@@ -582,23 +605,23 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     const int nsub = kBlock / width;
     for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
         const uint32_t j = list[q];
-        const uint4 rj = A.rec[j];
+        const uint4 rj = lrec[q];
         const uint32_t s = rj.w & 0xFFu;
         const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
         const int comp = compartment(T, x, y, z);
         Best b{kNone, 0u, 0.0f, -1};
         if (li < ncell) {
-            const float p[3] = {x, y, z};
+            const float pp[3] = {x, y, z};
             const int o[3] = {li % 3, (li / 3) % 3, li / 9};
             const int o8[3] = {li & 1, (li >> 1) & 1, li >> 2};
             int cc[3];
             bool inside = true;
             for (int a = 0; a < 3; ++a) {
-                const int c = int(cell_coord(T, p[a]));
+                const int c = int(cell_coord(T, pp[a]));
                 int v;
                 if (T.stencil8) {
                     // the neighbour on the side of the cell the point is nearer
-                    const float f = (p[a] - T.lo) * T.inv_h - float(c);
+                    const float f = (pp[a] - T.lo) * T.inv_h - float(c);
                     v = c + o8[a] * (f < 0.5f ? -1 : 1);
                 } else {
                     v = c + o[a] - 1;
@@ -608,10 +631,16 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
                 cc[a] = v;
             }
             if (inside) {
-                const uint32_t cell = uint32_t(cc[0]) + T.G * (uint32_t(cc[1]) + T.G * uint32_t(cc[2]));
+                const uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
                 const uint32_t e = d.cell_start[cell + 1];
-                for (uint32_t k = d.cell_start[cell]; k < e; ++k)
-                    consider(d, T, A, k, j, s, x, y, z, comp, b);
+                // candidates two at a time, both records requested together
+                for (uint32_t k = d.cell_start[cell]; k < e; k += 2) {
+                    const uint4 r0 = A.rec[k];
+                    const bool two = k + 1 < e;
+                    const uint4 r1 = two ? A.rec[k + 1] : r0;
+                    consider(d, T, A, r0, k, j, s, x, y, z, comp, b);
+                    if (two) consider(d, T, A, r1, k + 1, j, s, x, y, z, comp, b);
+                }
             }
         }
         reduce_best(b, width);
