@@ -32,13 +32,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 #            rank) pair (8)                                          = 44 B/agent
 #   scan:    reads the count, writes the start, clears the count     = 12 B/cell
 #   scatter: reads (key, rank), record, id, cell start (32); writes
-#            record, id, claimer byte, claim slot (29)               = 61 B/agent
+#            record, id, claimer byte (21)                           = 53 B/agent
 #   propose: claimer byte of the chunk (1 B/agent); per claimer its
 #            record and id (20) and its proposal (4)                 = 1 B/agent + 24 B/claimer
-#   finish:  claimer byte of the chunk (1 B/agent); per claimer its
-#            proposal (4)                                            = 1 B/agent + 4 B/claimer
-KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (61, 0, 0),
-                "propose": (1, 24, 0), "finish": (1, 4, 0)}
+#   finish:  per proposer only (a few hundred per step): counted as 0
+KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (53, 0, 0),
+                "propose": (1, 24, 0), "finish": (0, 0, 0)}
 
 
 def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:

@@ -79,7 +79,7 @@ bool config_ok(const mabm_config* c, std::string& why)
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
     size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_acc, slot,
-        prop, rkey, revent, rpartner, births, counts, total;
+        prop, plist, rkey, revent, rpartner, births, counts, total;
     uint32_t ncells, ntiles;
 };
 
@@ -111,6 +111,7 @@ Layout make_layout(const mabm_config& c)
     L.tile_acc = take((size_t)2 * L.ntiles * kTileStride * 4);
     L.slot = take(cap * 8);
     L.prop = take(cap * 4);
+    L.plist = take(cap * 4);
     L.rkey = take(cap * 4);
     L.revent = take(cap);
     L.rpartner = take(cap * 4);
@@ -316,6 +317,7 @@ void fill_dev(mabm_sim* s)
     d.tile_acc = (uint32_t*)(A + L.tile_acc);
     d.slot = (unsigned long long*)(A + L.slot);
     d.prop = (uint32_t*)(A + L.prop);
+    d.plist = (uint32_t*)(A + L.plist);
     d.rkey = (uint32_t*)(A + L.rkey);
     d.revent = A + L.revent;
     d.rpartner = (uint32_t*)(A + L.rpartner);
@@ -342,6 +344,8 @@ mabm_status finalize(mabm_sim* s, bool place)
     // cell counts and both parities' tile sums start at zero
     HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ntiles * kScanTile * 4, s->stream));
     HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
+    // claim slots are all-ones between steps (each step resets those it used)
+    HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.capacity * 8, s->stream));
     launch_fill_records(d, s->stream);
     if (place) launch_init(d, s->stream);
     HIP_OK(s, hipGetLastError());

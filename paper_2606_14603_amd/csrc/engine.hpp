@@ -83,6 +83,7 @@ struct Ctl {
     StepState s[2];
     uint32_t n_births[2];  // birth records appended by the step of parity p
     uint32_t holes[2];     // agents consumed by pair rules in the step of parity p
+    uint32_t n_prop[2];    // entries of the proposer list of the step of parity p
     uint32_t n_binned;     // agents binned in the current step
     uint32_t err;          // ErrBit, sticky
     unsigned long long agent_updates;  // sum of live agents at step starts
@@ -111,6 +112,7 @@ struct Dev {
                            // accumulated by move, one set per parity
     unsigned long long* slot;
     uint32_t* prop;        // per sorted agent: proposed partner index
+    uint32_t* plist;       // sorted indices of this step's proposing claimers
     uint32_t* rkey;        // record arrays, indexed like the current agents
     uint8_t* revent;
     uint32_t* rpartner;

@@ -206,6 +206,13 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
     const uint32_t t = d.ctl->s[p].t;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     const Agents A = d.a[p];
+    // claim slots start every step at all-ones: the previous step wrote only
+    // those of its proposers and their targets, which are reset here
+    if (i < d.ctl->n_prop[p ^ 1]) {
+        const uint32_t j = d.plist[i];
+        d.slot[j] = ~0ull;
+        d.slot[d.prop[j]] = ~0ull;
+    }
     uint32_t key = kNone;
     uint4 r = {0u, 0u, 0u, kDead};
     uint32_t id = 0;
@@ -451,6 +458,7 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
         ctl->agent_updates += cur.n_slots - ctl->holes[p ^ 1];
         ctl->holes[p ^ 1] = 0u;
         ctl->n_births[p ^ 1] = 0u;
+        ctl->n_prop[p ^ 1] = 0u;
         ctl->s[p ^ 1] = StepState{cur.t + 1u, nbin + nb, cur.next_id + nb, 0u};
     }
 }
@@ -458,7 +466,7 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
 // ---------------------------------------------------------------------------
 // scatter: binned agents to cell order in the other buffer; the claimer flag
 // (non-busy agent of a claiming species) is set in the record and in the
-// one-byte array the propose/finish chunks scan.
+// one-byte array the propose chunks scan.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 {
@@ -481,7 +489,6 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     B.rec[j] = r;
     B.id[j] = A.id[i];
     d.sclaim[j] = claim ? 1 : 0;
-    d.slot[j] = ~0ull;
     if (record) {
         d.rkey[j] = linear_cell(T, kr.x);
         d.revent[j] = d.event[i];
@@ -538,11 +545,19 @@ struct Best {
     int rule;
 };
 
-__device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Agents& A,
+// The pair-rule table and the contact radii live in LDS while a workgroup
+// searches: rule index of (claimer species, target species), -1 for none.
+struct PairLds {
+    int8_t rule_of[kMaxSpecies * kMaxSpecies];
+    float r2[kMaxRules];
+};
+
+__device__ __forceinline__ void consider(const Tables& T, const PairLds& P, const Agents& A,
                                          const uint4& rk, uint32_t k, uint32_t self, uint32_t s,
                                          float x, float y, float z, int comp, Best& b)
 {
-    const int r = T.rule_of[s][rk.w & 0xFFu];
+    const uint32_t sb = rk.w & 0xFFu;
+    const int r = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : -1;
     if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
     const float bx = __uint_as_float(rk.x), by = __uint_as_float(rk.y), bz = __uint_as_float(rk.z);
     if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
@@ -553,7 +568,7 @@ __device__ __forceinline__ void consider(const Dev& d, const Tables& T, const Ag
         if (dz > T.halfL) dz -= T.L; else if (dz < -T.halfL) dz += T.L;
     }
     const float d2 = dx * dx + dy * dy + dz * dz;
-    if (!(d2 <= T.rule[r].r2)) return;
+    if (!(d2 <= P.r2[r])) return;
     if (b.idx != kNone && d2 > b.d2) return;
     const uint32_t bid = A.id[k];
     if (b.idx == kNone || d2 < b.d2 || bid < b.id) {
@@ -583,18 +598,29 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint4 lrec[kPChunk];
-    __shared__ uint32_t count;
+    __shared__ uint32_t plocal[kPChunk];
+    __shared__ PairLds P;
+    __shared__ uint32_t count, nprop, pbase;
     const Tables& T = *d.tab;
     const uint32_t n = d.ctl->n_binned;
     const uint32_t t = d.ctl->s[p].t;
     const uint32_t first = xcd_chunk() * kPChunk;
     if (first >= n) return;
+    {
+        // rows of the species in use, as words; the radii of the rules
+        const uint32_t nw = uint32_t(T.ns) * (kMaxSpecies / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&T.rule_of[0][0]);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
+        for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
+    }
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
     // the chunk's claimers, then their records, compacted into LDS
     const uint32_t nl =
         compact_chunk(first, last, list, &count, [&](uint32_t k) { return d.sclaim[k] != 0; });
     for (uint32_t q = threadIdx.x; q < nl; q += kBlock) lrec[q] = A.rec[list[q]];
+    if (threadIdx.x == 0) nprop = 0;
     __syncthreads();
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
@@ -638,8 +664,8 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
                     const uint4 r0 = A.rec[k];
                     const bool two = k + 1 < e;
                     const uint4 r1 = two ? A.rec[k + 1] : r0;
-                    consider(d, T, A, r0, k, j, s, x, y, z, comp, b);
-                    if (two) consider(d, T, A, r1, k + 1, j, s, x, y, z, comp, b);
+                    consider(T, P, A, r0, k, j, s, x, y, z, comp, b);
+                    if (two) consider(T, P, A, r1, k + 1, j, s, x, y, z, comp, b);
                 }
             }
         }
@@ -656,11 +682,20 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
                     atomicMin(&d.slot[j], pr | b.id);
                     atomicMin(&d.slot[b.idx], pr | ida);
                     out = b.idx;
+                    plocal[atomicAdd(&nprop, 1u)] = j;
                 }
             }
             d.prop[j] = out;
         }
     }
+    // the workgroup's proposers join the step's proposer list (one global
+    // atomic per workgroup that has any)
+    __syncthreads();
+    const uint32_t np = nprop;
+    if (np == 0) return;
+    if (threadIdx.x == 0) pbase = atomicAdd(&d.ctl->n_prop[p], np);
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < np; q += kBlock) d.plist[pbase + q] = plocal[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -671,22 +706,17 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record)
 {
-    __shared__ uint32_t list[kPChunk];
-    __shared__ uint32_t count, s_holes;
+    __shared__ uint32_t s_holes;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
-    const uint32_t n = ctl->n_binned;
+    const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
-    const uint32_t first = xcd_chunk() * kPChunk;
-    if (first >= n) return;
+    if (blockIdx.x * kBlock >= np) return;
     if (threadIdx.x == 0) s_holes = 0;
-    const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
-    const uint32_t nl = compact_chunk(first, last, list, &count, [&](uint32_t k) {
-        return d.sclaim[k] && d.prop[k] != kNone;
-    });
+    __syncthreads();
     const Agents A = d.a[p ^ 1];
-    for (uint32_t q = threadIdx.x; q < nl; q += kBlock) {
-        const uint32_t j = list[q];
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < np; q += gridDim.x * kBlock) {
+        const uint32_t j = d.plist[q];
         const uint32_t b = d.prop[j];
         const uint32_t ida = A.id[j], idb = A.id[b];
         const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
@@ -742,6 +772,7 @@ __global__ void k_zero_counts(Dev d)
 // synchronisation and can be captured in a graph.
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
+static constexpr unsigned kFinishBlocks = 512;
 static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
@@ -768,7 +799,10 @@ void launch_propose(const Dev& d, int p, hipStream_t s)
 }
 void launch_finish(const Dev& d, int p, int record, hipStream_t s)
 {
-    k_finish<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, p, record);
+    // a fixed grid strides over the step's proposer list
+    unsigned nb = blocks_for(d.capacity);
+    if (nb > kFinishBlocks) nb = kFinishBlocks;
+    k_finish<<<nb, kBlock, 0, s>>>(d, p, record);
 }
 void launch_counts(const Dev& d, int cur, hipStream_t s)
 {
