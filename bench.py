@@ -6,13 +6,15 @@ is quoted at.  A step is one pass of the whole step (event draw, Brownian
 move, boundaries, binning, counting sort, neighbour scan + claim, rule
 firing, compaction).  Agent state is resident in HBM before timing starts.
 
-Prints one JSON line with the metric, the dominant kernel's roofline (HIP
-events on the simulation's stream over the timed region) and the CPU
-oracle's rate on a bounded sample of the same workload.
+Prints one JSON line with the metric, the dominant kernel's roofline (kernel
+durations from HIP events that each kernel's dispatch stamps at its start and
+end, on the simulation's stream) and the CPU oracle's rate on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +40,64 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 #   finish:  per proposer only (a few hundred per step): counted as 0
 KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (53, 0, 0),
                 "propose": (1, 24, 0), "finish": (0, 0, 0)}
+
+# move is bound by vector-ALU issue, not by HBM: the arithmetic the step
+# definition prescribes per agent (Philox4x32-10 block, event word and
+# threshold, four uniforms, two logarithms, two square roots, two sin/cos
+# evaluations, the displacement, the sphere test, the cell coordinates and
+# their Morton interleave), counted as 32-bit operations (a 32x32->64 product
+# = 2, a correctly rounded divide or square root = 1), is 339 per agent.
+MOVE_OPS_PER_AGENT = 339
+# One 32-bit lane operation per clock per lane: 256 CUs x 64 lanes x 2.4 GHz
+# (the 157.3 TFLOP/s fp32 figure counts an FMA as 2 and packed pairs as 2).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# HBM traffic of move per launch from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, averaged over 55 dispatches of
+# "bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile
+# --copy-calib-mb 512"), scaled by what the same counters read for the
+# 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
+# the kernel sources it was taken on (SHA-256 of the three files below).
+TRAFFIC = {"kernel": "move", "fetch_kib": 19691.5, "write_kib": 59000.1, "fetch_scale": 2.0,
+           "write_scale": 1.0,
+           "sources_sha256": "1ddeb0725353aeb3d6961768af1a23be285e02121ae183b33c9520c6a95930fe"}
+KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
+                  "paper_2606_14603_amd/csrc/device_math.hpp",
+                  "paper_2606_14603_amd/csrc/engine.hpp")
+
+
+def kernel_sources_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """Calibrated HBM bytes per launch, or None if the counters are stale."""
+    t = TRAFFIC
+    if t["kernel"] != kernel or t["fetch_kib"] is None or t["sources_sha256"] != kernel_sources_sha():
+        return None
+    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
+
+def copy_ceiling_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Achieved read+write GB/s of a plain device-to-device copy."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:
@@ -114,8 +174,8 @@ def main() -> int:
     counts, t = sim.counts()
     claimers = int(counts[[0, 3, 6]].sum())  # kinase1, p-kinase2, phosphatase claim
 
-    # same number of steps with HIP events around every kernel (direct
-    # launches: events cannot sit between graph nodes) for the roofline
+    # the same number of steps again, each kernel's dispatch stamping HIP
+    # events at its start and end (direct launches), for per-kernel durations
     roof, kernels, ms_direct = None, {}, None
     if not args.no_profile:
         sim.profile(True)
@@ -124,14 +184,31 @@ def main() -> int:
         sim.profile(False)
         for name, (launches, tot) in prof.items():
             if launches:
-                kernels[name] = {"launches": launches, "avg_us": round(1e3 * tot / launches, 3)}
+                a, q, c = KERNEL_BYTES[name]
+                alg = a * live + q * claimers + c * G ** 3
+                us = 1e3 * tot / launches
+                kernels[name] = {"launches": launches, "avg_us": round(us, 3),
+                                 "alg_bytes": int(alg), "alg_gbs": round(alg / us / 1e3, 1)}
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-        a, q, c = KERNEL_BYTES[dom]
-        alg = a * live + q * claimers + c * G ** 3
-        achieved = alg / (kernels[dom]["avg_us"] * 1e-6) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "alg_bytes_per_launch": int(alg)}
+        us = kernels[dom]["avg_us"]
+        if dom == "move":
+            ops = MOVE_OPS_PER_AGENT * live
+            achieved = ops / (us * 1e-6) / 1e12
+            roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 2),
+                    "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                    "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                    "alg_ops_per_launch": int(ops)}
+        else:
+            achieved = kernels[dom]["alg_gbs"]
+            roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        roof["traffic"] = measured_traffic(dom)
+        roof["alg_bytes_per_launch"] = kernels[dom]["alg_bytes"]
+        roof["hbm_frac_alg_bytes"] = round(kernels[dom]["alg_gbs"] / HBM_PEAK_GBS, 4)
+        step_bytes = sum(k["alg_bytes"] for k in kernels.values())
+        roof["step_alg_bytes_per_update"] = round(step_bytes / live, 1)
+        roof["step_alg_gbs"] = round(step_bytes * args.steps / (ms * 1e-3) / 1e9, 1)
+        roof["copy_ceiling_gbs"] = round(copy_ceiling_gbs(torch), 1)
     out = {
         "metric": METRIC, "value": value, "unit": "agent-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,

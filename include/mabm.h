@@ -177,10 +177,13 @@ mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uin
                         const float* x, const float* y, const float* z, uint32_t next_id,
                         uint32_t t);
 
-/* Per-kernel timing with HIP events recorded on the simulation's stream:
- * enable (1) or disable (0); read returns, per kernel of the step, the
- * number of launches timed and their total milliseconds (synchronises).
- * names receives a static string per kernel. */
+/* Per-kernel timing: while enabled (1), each step kernel is dispatched with
+ * a pair of HIP events that the dispatch itself stamps at the kernel's start
+ * and end, so the time is the kernel's own duration; steps then run as
+ * direct launches, somewhat slower than untimed ones.  Disable with 0.  read
+ * returns, per kernel of the step, the number of launches timed and their
+ * total milliseconds (synchronises); names receives a static string per
+ * kernel. */
 #define MABM_N_KERNELS 5
 mabm_status mabm_profile(mabm_sim* sim, int32_t enable);
 mabm_status mabm_profile_read(mabm_sim* sim, const char** names, uint64_t* launches,

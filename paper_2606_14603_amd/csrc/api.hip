@@ -189,20 +189,20 @@ void harvest(mabm_sim* s)
     s->pending = 0;
 }
 
+// Launch one step kernel; with timing on, its dispatch stamps a pooled
+// event pair at the kernel's start and end.
 template <class F>
 void timed(mabm_sim* s, int kid, F&& launch)
 {
     if (!s->prof) {
-        launch();
+        launch(KEvents{});
         return;
     }
     if (s->pending == s->pool.size()) harvest(s);
     EventPair& p = s->pool[s->pending];
     s->pending_kernel[s->pending] = kid;
     ++s->pending;
-    (void)hipEventRecord(p.a, s->stream);
-    launch();
-    (void)hipEventRecord(p.b, s->stream);
+    launch(KEvents{p.a, p.b});
 }
 
 mabm_status build_tables(mabm_sim* s)
@@ -516,12 +516,12 @@ void enqueue_step(mabm_sim* s, int p)
     const Dev& d = s->dev;
     const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
     hipStream_t q = s->stream;
-    timed(s, kKMove, [&] { launch_move(d, p, rec, q); });
-    timed(s, kKScan, [&] { launch_scan(d, p, q); });
-    timed(s, kKScatter, [&] { launch_scatter(d, p, rec, q); });
+    timed(s, kKMove, [&](const KEvents& e) { launch_move(d, p, rec, q, e); });
+    timed(s, kKScan, [&](const KEvents& e) { launch_scan(d, p, q, e); });
+    timed(s, kKScatter, [&](const KEvents& e) { launch_scatter(d, p, rec, q, e); });
     if (s->has_bimol) {
-        timed(s, kKPropose, [&] { launch_propose(d, p, q); });
-        timed(s, kKFinish, [&] { launch_finish(d, p, rec, q); });
+        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, q, e); });
+        timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, q, e); });
     }
 }
 

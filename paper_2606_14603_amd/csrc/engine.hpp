@@ -125,14 +125,21 @@ struct Dev {
 enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
+// Optional start/stop events of a step kernel: when set, the dispatch itself
+// timestamps them at the kernel's start and end (hipExtLaunchKernel), so the
+// elapsed time is the kernel's own duration without the marker packets.
+struct KEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // launch entry points (kernels.hip); each enqueues one kernel on `s`
 void launch_init(const Dev& d, hipStream_t s);
 // p: parity of the step (its agents start in a[p] and are sorted into a[p ^ 1])
-void launch_move(const Dev& d, int p, int record, hipStream_t s);
-void launch_scan(const Dev& d, int p, hipStream_t s);
-void launch_scatter(const Dev& d, int p, int record, hipStream_t s);
-void launch_propose(const Dev& d, int p, hipStream_t s);
-void launch_finish(const Dev& d, int p, int record, hipStream_t s);
+void launch_move(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
+void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
+void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
+void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
+void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
 void launch_counts(const Dev& d, int cur, hipStream_t s);
 void launch_fill_records(const Dev& d, hipStream_t s);
 

@@ -30,6 +30,8 @@
 // waits on another workgroup, and no hot loop puts many atomics on one
 // address or one 4 KiB page (they serialise at the memory side).  Nothing
 // here is a dense contraction.
+#include <hip/hip_ext.h>
+
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -783,26 +785,36 @@ void launch_fill_records(const Dev& d, hipStream_t s)
 {
     k_fill_records<<<blocks_for(d.capacity), kBlock, 0, s>>>(d);
 }
-void launch_move(const Dev& d, int p, int record, hipStream_t s)
+template <class K, class... Args>
+static inline void go(K kernel, unsigned grid, unsigned block, hipStream_t s, const KEvents& ev,
+                      Args... args)
 {
-    k_move<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, p, record);
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev.start, ev.stop, 0, args...);
 }
-void launch_scan(const Dev& d, int p, hipStream_t s) { k_scan<<<d.ntiles, kScanThreads, 0, s>>>(d, p); }
-void launch_scatter(const Dev& d, int p, int record, hipStream_t s)
+
+void launch_move(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
+{
+    go(k_move, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
+}
+void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
+{
+    go(k_scan, d.ntiles, kScanThreads, s, ev, d, p);
+}
+void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
     // one workgroup per 256 slots, plus the births/bookkeeping workgroup
-    k_scatter<<<blocks_for(d.capacity) + 1, kBlock, 0, s>>>(d, p, record);
+    go(k_scatter, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
 }
-void launch_propose(const Dev& d, int p, hipStream_t s)
+void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
-    k_propose<<<chunks_for(d.capacity), kBlock, 0, s>>>(d, p);
+    go(k_propose, chunks_for(d.capacity), kBlock, s, ev, d, p);
 }
-void launch_finish(const Dev& d, int p, int record, hipStream_t s)
+void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
     // a fixed grid strides over the step's proposer list
     unsigned nb = blocks_for(d.capacity);
     if (nb > kFinishBlocks) nb = kFinishBlocks;
-    k_finish<<<nb, kBlock, 0, s>>>(d, p, record);
+    go(k_finish, nb, kBlock, s, ev, d, p, record);
 }
 void launch_counts(const Dev& d, int cur, hipStream_t s)
 {
