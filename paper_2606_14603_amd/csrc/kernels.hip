@@ -42,7 +42,7 @@ const char* const kKernelNames[kNumKernels] = {"move", "scan", "scatter", "propo
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kPChunk = 512;  // sorted agents per workgroup of propose/finish
+constexpr int kPChunk = 1024;  // sorted agents per workgroup of propose
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -498,23 +498,28 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     }
 }
 
-// Compact, in LDS, the agents of this workgroup's chunk [first, last) that
-// satisfy `pred` (at most kPChunk = 2 x kBlock agents).  Each thread tests
-// its two agents before any list write, so the loads they need are in
-// flight together; one LDS atomic per wave reserves the list space.
-// Returns the list length.
-template <class Pred>
-__device__ __forceinline__ uint32_t compact_chunk(uint32_t first, uint32_t last, uint32_t* list,
-                                                  uint32_t* count, Pred pred)
+// Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
+// kPChunk = 4 x kBlock sorted agents: each thread reads the four claimer
+// flags of its agents as one word, a wave-level prefix places them, and one
+// LDS atomic per wave reserves the list space.  Returns the list length.
+__device__ __forceinline__ uint32_t compact_claimers(const uint8_t* sclaim, uint32_t first,
+                                                     uint32_t last, uint32_t* list,
+                                                     uint32_t* count)
 {
-    static_assert(kPChunk == 2 * kBlock, "two agents per thread");
+    static_assert(kPChunk == 4 * kBlock, "four agents per thread");
     if (threadIdx.x == 0) *count = 0;
     __syncthreads();
-    const uint32_t k0 = first + 2u * threadIdx.x, k1 = k0 + 1u;
-    const bool c0 = k0 < last && pred(k0);
-    const bool c1 = k1 < last && pred(k1);
-    const uint32_t mine = (c0 ? 1u : 0u) + (c1 ? 1u : 0u);
-    // wave-level exclusive prefix of the per-thread counts
+    const uint32_t k0 = first + 4u * threadIdx.x;
+    uint32_t flags = 0;
+    if (k0 < last) {
+        // the chunk start is a multiple of 4, the arena rounds every array to
+        // 256 bytes, so the word is in bounds; flags past `last` are dropped
+        flags = *reinterpret_cast<const uint32_t*>(sclaim + k0);
+        const uint32_t valid = last - k0 >= 4u ? 4u : last - k0;
+        if (valid < 4u) flags &= (1u << (8u * valid)) - 1u;
+    }
+    const uint32_t mine = (flags & 0xFFu ? 1u : 0u) + (flags & 0xFF00u ? 1u : 0u) +
+                          (flags & 0xFF0000u ? 1u : 0u) + (flags & 0xFF000000u ? 1u : 0u);
     uint32_t incl = mine;
     const int lane = lane_id();
 #pragma unroll
@@ -526,8 +531,9 @@ __device__ __forceinline__ uint32_t compact_chunk(uint32_t first, uint32_t last,
     uint32_t base = 0;
     if (lane == 0 && wave_total) base = atomicAdd(count, wave_total);
     base = __shfl(base, 0, 64) + incl - mine;
-    if (c0) list[base++] = k0;
-    if (c1) list[base] = k1;
+#pragma unroll
+    for (uint32_t b = 0; b < 4u; ++b)
+        if ((flags >> (8u * b)) & 0xFFu) list[base++] = k0 + b;
     __syncthreads();
     return *count;
 }
@@ -536,8 +542,8 @@ __device__ __forceinline__ uint32_t compact_chunk(uint32_t first, uint32_t last,
 // propose (O7): for each claimer, the eligible partner minimising (d^2, id)
 // over the 8-cell (h >= 2 R_max) or 27-cell stencil, then a Bernoulli draw,
 // then the handshake key into both claim slots by atomic minimum.  A
-// workgroup takes 512 sorted agents; their claimers are searched by
-// subgroups of 8 (or 32) lanes, one stencil cell per lane, and the lanes'
+// workgroup takes 1024 sorted agents; their claimers are searched by
+// subgroups of 4 (or 16) lanes, two stencil cells per lane, and the lanes'
 // best candidates are reduced by shuffles, so each claimer's dependent
 // chain of loads is a few round trips long.
 // ---------------------------------------------------------------------------
@@ -599,7 +605,6 @@ __device__ __forceinline__ void reduce_best(Best& b, int width)
 __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 {
     __shared__ uint32_t list[kPChunk];
-    __shared__ uint4 lrec[kPChunk];
     __shared__ uint32_t plocal[kPChunk];
     __shared__ PairLds P;
     __shared__ uint32_t count, nprop, pbase;
@@ -615,61 +620,73 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
         uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
         for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
         for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
+        if (threadIdx.x == 0) nprop = 0;
     }
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
-    // the chunk's claimers, then their records, compacted into LDS
-    const uint32_t nl =
-        compact_chunk(first, last, list, &count, [&](uint32_t k) { return d.sclaim[k] != 0; });
-    for (uint32_t q = threadIdx.x; q < nl; q += kBlock) lrec[q] = A.rec[list[q]];
-    if (threadIdx.x == 0) nprop = 0;
-    __syncthreads();
+    const uint32_t nl = compact_claimers(d.sclaim, first, last, list, &count);
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
-    // a subgroup of `width` lanes per claimer, one stencil cell per lane
-    const int width = T.stencil8 ? 8 : 32;
+    // a subgroup of `width` lanes per claimer, two stencil cells per lane
+    const int width = T.stencil8 ? 4 : 16;
     const int ncell = T.stencil8 ? 8 : 27;
     const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
     const int nsub = kBlock / width;
     for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
         const uint32_t j = list[q];
-        const uint4 rj = lrec[q];
+        const uint4 rj = A.rec[j];
         const uint32_t s = rj.w & 0xFFu;
         const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
         const int comp = compartment(T, x, y, z);
-        Best b{kNone, 0u, 0.0f, -1};
-        if (li < ncell) {
-            const float pp[3] = {x, y, z};
-            const int o[3] = {li % 3, (li / 3) % 3, li / 9};
-            const int o8[3] = {li & 1, (li >> 1) & 1, li >> 2};
+        const float pp[3] = {x, y, z};
+        int c[3];
+        float f[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = int(cell_coord(T, pp[a]));
+            f[a] = (pp[a] - T.lo) * T.inv_h - float(c[a]);
+        }
+        // candidate range of stencil cell m (empty outside the grid)
+        auto range = [&](int m, uint32_t& lo, uint32_t& hi) {
+            lo = hi = 0;
+            if (m >= ncell) return;
             int cc[3];
-            bool inside = true;
             for (int a = 0; a < 3; ++a) {
-                const int c = int(cell_coord(T, pp[a]));
                 int v;
                 if (T.stencil8) {
                     // the neighbour on the side of the cell the point is nearer
-                    const float f = (pp[a] - T.lo) * T.inv_h - float(c);
-                    v = c + o8[a] * (f < 0.5f ? -1 : 1);
+                    const int bit = (m >> a) & 1;
+                    v = c[a] + bit * (f[a] < 0.5f ? -1 : 1);
                 } else {
-                    v = c + o[a] - 1;
+                    const int o = a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9);
+                    v = c[a] + o - 1;
                 }
                 if (periodic) v = (v + G) % G;
-                else if (v < 0 || v >= G) inside = false;
+                else if (v < 0 || v >= G) return;
                 cc[a] = v;
             }
-            if (inside) {
-                const uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
-                const uint32_t e = d.cell_start[cell + 1];
-                // candidates two at a time, both records requested together
-                for (uint32_t k = d.cell_start[cell]; k < e; k += 2) {
-                    const uint4 r0 = A.rec[k];
-                    const bool two = k + 1 < e;
-                    const uint4 r1 = two ? A.rec[k + 1] : r0;
-                    consider(T, P, A, r0, k, j, s, x, y, z, comp, b);
-                    if (two) consider(T, P, A, r1, k + 1, j, s, x, y, z, comp, b);
-                }
-            }
+            const uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
+            lo = d.cell_start[cell];
+            hi = d.cell_start[cell + 1];
+        };
+        uint32_t k0, e0, k1, e1;
+        range(li, k0, e0);
+        range(li + width, k1, e1);
+        Best b{kNone, 0u, 0.0f, -1};
+        // up to two candidates of each cell per round, all four records
+        // requested together
+        while (k0 < e0 || k1 < e1) {
+            const bool a0 = k0 < e0, a1 = k0 + 1 < e0, b0 = k1 < e1, b1 = k1 + 1 < e1;
+            uint4 r0{}, r1{}, r2{}, r3{};
+            if (a0) r0 = A.rec[k0];
+            if (a1) r1 = A.rec[k0 + 1];
+            if (b0) r2 = A.rec[k1];
+            if (b1) r3 = A.rec[k1 + 1];
+            if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, b);
+            if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, b);
+            if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, b);
+            if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, b);
+            k0 += 2;
+            k1 += 2;
         }
         reduce_best(b, width);
         if (li == 0) {
@@ -774,7 +791,7 @@ __global__ void k_zero_counts(Dev d)
 // synchronisation and can be captured in a graph.
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
-static constexpr unsigned kFinishBlocks = 512;
+static constexpr unsigned kFinishBlocks = 64;
 static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
