@@ -104,7 +104,7 @@ Layout make_layout(const mabm_config& c)
     }
     L.kr = take(cap * 8);
     L.event = take(cap);
-    L.sclaim = take(cap);
+    L.sclaim = take((cap + kClaimChunk - 1) / kClaimChunk * kClaimChunk);
     const size_t padded = (size_t)L.ntiles * kScanTile;  // whole scan tiles
     L.cell_count = take(padded * 4);
     L.cell_start = take((padded + 1) * 4);

@@ -27,6 +27,9 @@ constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 
 constexpr int kScanItems = 8;                 // cells per thread in the scan
 constexpr int kScanThreads = 256;
 constexpr int kScanTile = kScanItems * kScanThreads;
+// sorted agents per workgroup of the neighbour search; the claimer-flag
+// array is padded to a whole number of these
+constexpr uint32_t kClaimChunk = 1024;
 
 // Philox counter "purpose" words (third counter word; 1 is unused: the
 // event draw shares the MOVE block).

@@ -42,7 +42,7 @@ const char* const kKernelNames[kNumKernels] = {"move", "scan", "scatter", "propo
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kPChunk = 1024;  // sorted agents per workgroup of propose
+constexpr int kPChunk = int(kClaimChunk);  // sorted agents per workgroup of propose
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -502,19 +502,18 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 // kPChunk = 4 x kBlock sorted agents: each thread reads the four claimer
 // flags of its agents as one word, a wave-level prefix places them, and one
 // LDS atomic per wave reserves the list space.  Returns the list length.
-__device__ __forceinline__ uint32_t compact_claimers(const uint8_t* sclaim, uint32_t first,
-                                                     uint32_t last, uint32_t* list,
-                                                     uint32_t* count)
+// `word` is the thread's flag word, loaded by the caller before anything
+// else so that its latency overlaps the kernel's other set-up loads; the
+// caller has zeroed *count before a barrier.
+__device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t first, uint32_t last,
+                                                     uint32_t* list, uint32_t* count)
 {
     static_assert(kPChunk == 4 * kBlock, "four agents per thread");
-    if (threadIdx.x == 0) *count = 0;
-    __syncthreads();
     const uint32_t k0 = first + 4u * threadIdx.x;
     uint32_t flags = 0;
     if (k0 < last) {
-        // the chunk start is a multiple of 4, the arena rounds every array to
-        // 256 bytes, so the word is in bounds; flags past `last` are dropped
-        flags = *reinterpret_cast<const uint32_t*>(sclaim + k0);
+        // flags past `last` are dropped
+        flags = word;
         const uint32_t valid = last - k0 >= 4u ? 4u : last - k0;
         if (valid < 4u) flags &= (1u << (8u * valid)) - 1u;
     }
@@ -609,9 +608,14 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     __shared__ PairLds P;
     __shared__ uint32_t count, nprop, pbase;
     const Tables& T = *d.tab;
+    const uint32_t first = xcd_chunk() * kPChunk;
+    // The thread's four claimer flags, requested first.  The flag array is
+    // padded to whole chunks and the grid covers the capacity, so the word
+    // is in bounds even past the live agents (whose count arrives with the
+    // control block).
+    const uint32_t word = *reinterpret_cast<const uint32_t*>(d.sclaim + first + 4u * threadIdx.x);
     const uint32_t n = d.ctl->n_binned;
     const uint32_t t = d.ctl->s[p].t;
-    const uint32_t first = xcd_chunk() * kPChunk;
     if (first >= n) return;
     {
         // rows of the species in use, as words; the radii of the rules
@@ -620,11 +624,15 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
         uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
         for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
         for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
-        if (threadIdx.x == 0) nprop = 0;
+        if (threadIdx.x == 0) {
+            nprop = 0;
+            count = 0;
+        }
     }
+    __syncthreads();
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
-    const uint32_t nl = compact_claimers(d.sclaim, first, last, list, &count);
+    const uint32_t nl = compact_claimers(word, first, last, list, &count);
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
     // a subgroup of `width` lanes per claimer, two stencil cells per lane
