@@ -346,44 +346,52 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
 }
 
 // exclusive scan over the 256-thread block; the block total in *total
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
+// Exclusive prefix of v and the block totals of v and r, with one exchange
+// through LDS.
+__device__ __forceinline__ uint32_t block_excl_scan_sum(uint32_t v, uint32_t r, uint32_t* total_v,
+                                                        uint32_t* total_r)
 {
-    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t wsum[2][kScanThreads / 64];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const uint32_t inc = wave_incl_scan(v);
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    uint32_t off = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < kScanThreads / 64; ++k) {
-        if (k < wv) off += wsum[k];
-        tot += wsum[k];
+    const uint32_t rr = wave_incl_scan(r);
+    if (lane == 63) {
+        wsum[0][wv] = inc;
+        wsum[1][wv] = rr;
     }
     __syncthreads();
-    *total = tot;
+    uint32_t off = 0, tot = 0, totr = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) {
+        if (k < wv) off += wsum[0][k];
+        tot += wsum[0][k];
+        totr += wsum[1][k];
+    }
+    *total_v = tot;
+    *total_r = totr;
     return off + inc - v;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 {
     const uint32_t tile = blockIdx.x;
-    const uint32_t* acc = tile_acc(d, p);
-    uint32_t before = 0;
-    for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += acc[size_t(k) * kTileStride];
-    uint32_t prefix;
-    block_excl_scan(before, &prefix);
+    // the tile's own counts are requested before the preceding tiles' sums,
+    // so both loads are in flight together
     const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
     constexpr int kVec = kScanItems / 4;
     uint4* cnt4 = reinterpret_cast<uint4*>(d.cell_count + base);
     uint4 v[kVec];
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) v[k] = cnt4[k];
+    const uint32_t* acc = tile_acc(d, p);
+    uint32_t before = 0;
+    for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += acc[size_t(k) * kTileStride];
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) {
-        v[k] = cnt4[k];
-        sum += v[k].x + v[k].y + v[k].z + v[k].w;
-    }
-    uint32_t total;
-    uint32_t run = prefix + block_excl_scan(sum, &total);
+    for (int k = 0; k < kVec; ++k) sum += v[k].x + v[k].y + v[k].z + v[k].w;
+    uint32_t prefix, total;
+    uint32_t run = block_excl_scan_sum(sum, before, &total, &prefix);
+    run += prefix;
     uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + base);
 #pragma unroll
     for (int k = 0; k < kVec; ++k) {
