@@ -177,6 +177,61 @@ mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uin
                         const float* x, const float* y, const float* z, uint32_t next_id,
                         uint32_t t);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent simulations of one model stepped together.
+ *
+ * A dose x replicate sweep runs the same species and rules many times with
+ * different seeds, volume sizes and initial counts (the paper's dose-response
+ * study, Sec. 3.1, and its multiple-seed runs, Sec. 3.2).  A batch holds
+ * n_sims such simulations in one arena; every step is one set of kernel
+ * launches over all their agents (cells of different simulations never
+ * meet), so small simulations no longer pay the launch latency one by one.
+ * Each simulation's trajectory is identical, bit for bit, to the one
+ * mabm_create_sim gives for its configuration and counts.
+ *
+ * The configurations must agree on geometry, dt_s and flags; seed, volume
+ * size, capacity and cell size may differ; 1 <= n_sims <= 65535 and the
+ * summed capacity is at most 2^30.  On a batch handle, mabm_add_species,
+ * mabm_add_rule and mabm_step act on every simulation; mabm_add_species's
+ * initial_count applies to all of them until mabm_set_initial_counts sets
+ * one count per simulation; mabm_counts returns the per-species totals over
+ * the batch; mabm_grid gives simulation 0's grid; mabm_size, mabm_export and
+ * mabm_import are E_STATE (use the mabm_batch_* calls).  The 4,096 births per
+ * step are shared by the whole batch.
+ * ---------------------------------------------------------------------- */
+
+/* Device bytes of a batch (0 if the configurations are invalid or
+ * inconsistent); mabm_arena_bytes(cfg, ...) equals it with n_sims = 1. */
+size_t mabm_batch_arena_bytes(const mabm_config* cfgs, uint32_t n_sims, uint32_t n_species,
+                              uint32_t n_rules);
+
+/* Create a batch of n_sims simulations (cfgs[k] for simulation k) in one
+ * device arena, on one HIP stream; same ownership and errors as
+ * mabm_create_sim. */
+mabm_status mabm_create_batch(const mabm_config* cfgs, uint32_t n_sims, void* device_arena,
+                              size_t arena_bytes, void* hip_stream, mabm_sim** out);
+
+/* Initial counts of one species, one per simulation (counts has n_sims
+ * entries; Sec. 3.1's doses are initial inhibitor counts).  Before
+ * finalize; E_INVALID for an unknown species. */
+mabm_status mabm_set_initial_counts(mabm_sim* sim, int32_t species_id, const uint32_t* counts);
+
+/* Per-(simulation, species) live counts: out[k * n_species + s] for
+ * simulation k; out has n_sims * n_species entries.  Synchronises. */
+mabm_status mabm_batch_counts(mabm_sim* sim, uint64_t* out, uint32_t n_species,
+                              uint64_t* out_step);
+
+/* mabm_size, mabm_export and mabm_grid of simulation sim_index (also valid
+ * on a single simulation with sim_index 0).  E_INVALID for an index out of
+ * range. */
+mabm_status mabm_batch_size(mabm_sim* sim, uint32_t sim_index, uint32_t* n_live,
+                            uint32_t* next_id);
+mabm_status mabm_batch_export(mabm_sim* sim, uint32_t sim_index, uint32_t capacity, uint32_t* id,
+                              uint8_t* species, float* x, float* y, float* z, uint32_t* key,
+                              int32_t* event, uint32_t* partner);
+mabm_status mabm_batch_grid(mabm_sim* sim, uint32_t sim_index, uint32_t* cells_per_axis,
+                            float* cell_um);
+
 /* Per-kernel timing: while enabled (1), each step kernel is dispatched with
  * a pair of HIP events that the dispatch itself stamps at the kernel's start
  * and end, so the time is the kernel's own duration; steps then run as

@@ -80,12 +80,22 @@ def lib() -> ctypes.CDLL:
         L.mabm_profile_read.argtypes = [P, P, P, P]
         L.mabm_agent_updates.argtypes = [P, P]
         L.mabm_destroy_sim.argtypes = [P]
+        L.mabm_batch_arena_bytes.restype = c.c_size_t
+        L.mabm_batch_arena_bytes.argtypes = [P, c.c_uint32, c.c_uint32, c.c_uint32]
+        L.mabm_create_batch.argtypes = [P, c.c_uint32, P, c.c_size_t, P, c.POINTER(P)]
+        L.mabm_set_initial_counts.argtypes = [P, c.c_int32, P]
+        L.mabm_batch_counts.argtypes = [P, P, c.c_uint32, P]
+        L.mabm_batch_size.argtypes = [P, c.c_uint32, P, P]
+        L.mabm_batch_export.argtypes = [P, c.c_uint32, c.c_uint32, P, P, P, P, P, P, P, P]
+        L.mabm_batch_grid.argtypes = [P, c.c_uint32, c.POINTER(c.c_uint32), c.POINTER(c.c_float)]
         L.mabm_last_error.restype = c.c_char_p
         L.mabm_last_error.argtypes = [P]
         for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
                      "mabm_step", "mabm_counts", "mabm_size", "mabm_export", "mabm_import",
                      "mabm_profile", "mabm_profile_read", "mabm_agent_updates",
-                     "mabm_destroy_sim"):
+                     "mabm_destroy_sim", "mabm_create_batch", "mabm_set_initial_counts",
+                     "mabm_batch_counts", "mabm_batch_size", "mabm_batch_export",
+                     "mabm_batch_grid"):
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -140,6 +150,10 @@ class Sim:
         if rc != OK:
             raise MabmError(rc, L.mabm_last_error(None).decode())
         self._h = h
+        self._add_model(model)
+
+    def _add_model(self, model):
+        L, h = lib(), self._h
         out = ctypes.c_int32()
         for sp in model.species:
             self._chk(L.mabm_add_species(h, sp.name.encode(), float(sp.diffusion_um2_s),
@@ -222,3 +236,94 @@ class Sim:
         out = np.zeros(1, np.uint64)
         self._chk(lib().mabm_agent_updates(self._h, _ptr(out)))
         return int(out[0])
+
+
+def _same_structure(a, b) -> bool:
+    sa = [(x.name, float(x.diffusion_um2_s), int(x.compartment)) for x in a.species]
+    sb = [(x.name, float(x.diffusion_um2_s), int(x.compartment)) for x in b.species]
+    return (sa == sb and list(a.rules) == list(b.rules) and a.geometry == b.geometry
+            and a.dt_s == b.dt_s)
+
+
+def batch_arena_bytes(models, record: bool = False) -> int:
+    cfgs = (Config * len(models))(*[make_config(m, record) for m in models])
+    return int(lib().mabm_batch_arena_bytes(ctypes.cast(cfgs, ctypes.c_void_p), len(models),
+                                            len(models[0].species), len(models[0].rules)))
+
+
+class Batch(Sim):
+    """Many simulations of one model (same species, rules, geometry and dt)
+    stepped together by one set of launches per step; each keeps its own
+    seed, volume, capacity and initial counts (``models[k]`` for simulation
+    k), and its trajectory is the one ``Sim(models[k])`` gives."""
+
+    def __init__(self, models, record: bool = False, stream=None, device: str = "cuda",
+                 arena=None, graphs: bool = False):
+        import torch
+        L = lib()
+        if not models:
+            raise MabmError(E_INVALID, "empty batch")
+        m0 = models[0]
+        for m in models[1:]:
+            if not _same_structure(m0, m):
+                raise MabmError(E_INVALID, f"{m.name}: a batch shares species, rules, geometry, dt")
+        self.n_sims = len(models)
+        self.n_species = len(m0.species)
+        self.cfgs = (Config * self.n_sims)(*[make_config(m, record, None, None, graphs)
+                                             for m in models])
+        nbytes = int(L.mabm_batch_arena_bytes(ctypes.cast(self.cfgs, ctypes.c_void_p),
+                                              self.n_sims, self.n_species, len(m0.rules)))
+        if nbytes == 0:
+            raise MabmError(E_INVALID, "invalid batch configuration")
+        self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                                  device=device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.arena.device)
+            stream.wait_stream(torch.cuda.current_stream(self.arena.device))
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = L.mabm_create_batch(ctypes.cast(self.cfgs, ctypes.c_void_p), self.n_sims,
+                                 ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise MabmError(rc, L.mabm_last_error(None).decode())
+        self._h = h
+        self._add_model(m0)
+        for k in range(self.n_species):
+            c = np.array([int(m.species[k].count) for m in models], np.uint32)
+            self._chk(L.mabm_set_initial_counts(h, k, _ptr(c)))
+
+    def counts(self):
+        """(n_sims, n_species) live counts and the step counter."""
+        out = np.zeros(self.n_sims * self.n_species, np.uint64)
+        t = np.zeros(1, np.uint64)
+        self._chk(lib().mabm_batch_counts(self._h, _ptr(out), self.n_species, _ptr(t)))
+        return out.reshape(self.n_sims, self.n_species), int(t[0])
+
+    def size(self, k: int = 0):
+        n = np.zeros(1, np.uint32)
+        nid = np.zeros(1, np.uint32)
+        self._chk(lib().mabm_batch_size(self._h, int(k), _ptr(n), _ptr(nid)))
+        return int(n[0]), int(nid[0])
+
+    def grid(self, k: int = 0):
+        g = ctypes.c_uint32()
+        h = ctypes.c_float()
+        self._chk(lib().mabm_batch_grid(self._h, int(k), ctypes.byref(g), ctypes.byref(h)))
+        return int(g.value), float(h.value)
+
+    def export(self, k: int = 0) -> dict:
+        n, _ = self.size(k)
+        m = max(n, 1)
+        out = dict(id=np.zeros(m, np.uint32), species=np.zeros(m, np.uint8),
+                   x=np.zeros(m, np.float32), y=np.zeros(m, np.float32),
+                   z=np.zeros(m, np.float32), key=np.zeros(m, np.uint32),
+                   event=np.zeros(m, np.int32), partner=np.zeros(m, np.uint32))
+        self._chk(lib().mabm_batch_export(self._h, int(k), m,
+                                          *(_ptr(out[f]) for f in
+                                            ("id", "species", "x", "y", "z", "key", "event",
+                                             "partner"))))
+        return {f: v[:n] for f, v in out.items()}
+
+    def import_state(self, *a, **kw):
+        raise MabmError(E_STATE, "a batch cannot import a state")

@@ -79,11 +79,15 @@ bool config_ok(const mabm_config* c, std::string& why)
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
     size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_acc, slot,
-        prop, plist, rkey, revent, rpartner, births, counts, total;
+        prop, plist, rkey, revent, rpartner, births, counts, next_id, total;
     uint32_t ncells, ntiles;
 };
 
-Layout make_layout(const mabm_config& c)
+// Layout of one simulation (n = 1) or of a batch of n: agent arrays sized
+// for the summed capacities, the simulations' cell grids one after another
+// (each at most 8^bits of its configured grid; a contact radius can only
+// coarsen it), one table set and one id counter per simulation.
+Layout make_layout(const mabm_config* cs, uint32_t n)
 {
     Layout L{};
     size_t off = 0;
@@ -92,12 +96,15 @@ Layout make_layout(const mabm_config& c)
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t cap = c.capacity;
-    const uint32_t b = morton_bits(grid_from_config(c));
-    L.ncells = 1u << (3 * b);
-    L.ntiles = (L.ncells + kScanTile - 1) / kScanTile;
+    size_t cap = 0, cells = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        cap += cs[k].capacity;
+        cells += (size_t)1 << (3 * morton_bits(grid_from_config(cs[k])));
+    }
+    L.ncells = (uint32_t)cells;
+    L.ntiles = (uint32_t)((cells + kScanTile - 1) / kScanTile);
     L.ctl = take(sizeof(Ctl));
-    L.tab = take(sizeof(Tables));
+    L.tab = take(sizeof(Tables) * n);
     for (int b = 0; b < 2; ++b) {
         L.rec[b] = take(cap * 16);
         L.id[b] = take(cap * 4);
@@ -116,9 +123,18 @@ Layout make_layout(const mabm_config& c)
     L.revent = take(cap);
     L.rpartner = take(cap * 4);
     L.births = take((size_t)kMaxBirthsPerStep * sizeof(Birth));
-    L.counts = take(kMaxSpecies * 8);
+    L.counts = take((size_t)kMaxSpecies * 8 * n);
+    L.next_id = take((size_t)4 * n);
     L.total = off;
     return L;
+}
+
+// total capacity of a batch, 0 if it does not fit the 32-bit slot indices
+uint64_t total_capacity(const mabm_config* cs, uint32_t n)
+{
+    uint64_t cap = 0;
+    for (uint32_t k = 0; k < n; ++k) cap += cs[k].capacity;
+    return cap;
 }
 
 uint64_t threshold_of(double p)
@@ -130,13 +146,19 @@ uint64_t threshold_of(double p)
 }  // namespace
 
 struct mabm_sim {
-    mabm_config cfg{};
+    mabm_config cfg{};                 // the first simulation's configuration
+    std::vector<mabm_config> cfgs;     // one per simulation (a single one: {cfg})
+    uint32_t n_sims = 1;
+    std::vector<std::vector<uint32_t>> sim_counts;  // [species][simulation] initial counts
+    std::vector<Tables> tabs;          // one per simulation
+    std::vector<uint32_t> sim_G;
+    std::vector<float> sim_h;
+    std::vector<uint32_t> host_next_id;  // staging for the per-simulation id counters
     hipStream_t stream = nullptr;
     uint8_t* arena = nullptr;
     size_t arena_bytes = 0;
     Layout lay{};
     Dev dev{};
-    Tables tab{};
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
@@ -160,6 +182,13 @@ mabm_status fail(mabm_sim* s, mabm_status code, const std::string& msg)
 {
     s->err = msg;
     return code;
+}
+
+bool is_batch(mabm_sim* s, const char* call)
+{
+    if (s->n_sims == 1) return false;
+    s->err = std::string(call) + " refers to one simulation; this handle holds a batch";
+    return true;
 }
 
 mabm_status hip_fail(mabm_sim* s, hipError_t e, const char* what)
@@ -205,11 +234,11 @@ void timed(mabm_sim* s, int kid, F&& launch)
     launch(KEvents{p.a, p.b});
 }
 
-mabm_status build_tables(mabm_sim* s)
+// tables of simulation k of s (the only one, or one of a batch)
+mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
 {
-    Tables& T = s->tab;
     std::memset(&T, 0, sizeof T);
-    const mabm_config& c = s->cfg;
+    const mabm_config& c = s->cfgs[k_sim];
     const int ns = (int)s->species.size(), nr = (int)s->rules.size();
     if (ns == 0) return fail(s, MABM_E_INVALID, "no species");
     T.geometry = c.geometry;
@@ -226,7 +255,7 @@ mabm_status build_tables(mabm_sim* s)
     T.key1 = (uint32_t)(c.seed >> 32);
     uint64_t acc = 0;
     for (int k = 0; k < ns; ++k) {
-        acc += s->species[k].count;
+        acc += s->sim_counts[k][k_sim];
         T.init_end[k] = (uint32_t)acc;
         T.init_comp[k] = s->species[k].comp;
         T.sigma[k] = (float)std::sqrt(2.0 * (double)s->species[k].D * (double)c.dt_s);
@@ -288,13 +317,41 @@ mabm_status build_tables(mabm_sim* s)
         G = (uint32_t)std::floor(ext / (1.01 * rmax));
         if (G < 3) return fail(s, MABM_E_INVALID, "volume smaller than 3 cells of the contact radius");
     }
-    s->G = G;
-    s->h = (float)(ext / G);
+    s->sim_G[k_sim] = G;
+    s->sim_h[k_sim] = (float)(ext / G);
     T.G = G;
     T.morton_bits = morton_bits(G);
     T.lo = c.geometry == MABM_PERIODIC_BOX ? 0.0f : -c.outer_radius_um;
     T.inv_h = (float)((double)G / ext);
     T.stencil8 = (rmax > 0.0 && ext / G >= 2.02 * rmax) ? 1u : 0u;
+    return MABM_OK;
+}
+
+// every simulation's tables, and their places in the batch: cells and
+// initial slots one simulation after another; the 8-cell stencil only if
+// every simulation allows it (the search then has one lane layout)
+mabm_status build_tables(mabm_sim* s)
+{
+    const uint32_t n = s->n_sims;
+    s->tabs.assign(n, Tables{});
+    s->sim_G.assign(n, 0u);
+    s->sim_h.assign(n, 0.0f);
+    uint64_t cell_base = 0, slot_base = 0;
+    uint32_t stencil8 = 1;
+    for (uint32_t k = 0; k < n; ++k) {
+        Tables& T = s->tabs[k];
+        mabm_status st = build_one(s, k, T);
+        if (st != MABM_OK) return st;
+        T.sim = k;
+        T.cell_base = (uint32_t)cell_base;
+        T.slot_base = (uint32_t)slot_base;
+        cell_base += (uint64_t)1 << (3 * T.morton_bits);
+        slot_base += T.init_end[T.ns - 1];
+        stencil8 &= T.stencil8;
+    }
+    for (Tables& T : s->tabs) T.stencil8 = stencil8;
+    s->G = s->sim_G[0];
+    s->h = s->sim_h[0];
     return MABM_OK;
 }
 
@@ -323,7 +380,9 @@ void fill_dev(mabm_sim* s)
     d.rpartner = (uint32_t*)(A + L.rpartner);
     d.births = (Birth*)(A + L.births);
     d.counts = (unsigned long long*)(A + L.counts);
-    d.capacity = s->cfg.capacity;
+    d.next_id = (uint32_t*)(A + L.next_id);
+    d.capacity = (uint32_t)total_capacity(s->cfgs.data(), s->n_sims);
+    d.n_sims = s->n_sims;
 }
 
 // first step / query / import: tables, hash geometry, upload, placement
@@ -334,20 +393,38 @@ mabm_status finalize(mabm_sim* s, bool place)
     mabm_status st = build_tables(s);
     if (st != MABM_OK) return st;
     Dev& d = s->dev;
-    d.ncells = 1u << (3 * s->tab.morton_bits);
+    const Tables& last = s->tabs.back();
+    d.ncells = last.cell_base + (1u << (3 * last.morton_bits));
     d.ntiles = (d.ncells + kScanTile - 1) / kScanTile;
-    d.n_init = place ? s->tab.init_end[s->tab.ns - 1] : 0;
-    HIP_OK(s, hipMemcpyAsync((void*)d.tab, &s->tab, sizeof(Tables), hipMemcpyHostToDevice, s->stream));
+    // agents placed: every simulation's initial counts, one after another
+    std::vector<uint32_t> n_init(s->n_sims);
+    uint32_t total = 0;
+    for (uint32_t k = 0; k < s->n_sims; ++k) {
+        n_init[k] = place ? s->tabs[k].init_end[s->tabs[k].ns - 1] : 0;
+        total += n_init[k];
+    }
+    d.n_init = total;
+    HIP_OK(s, hipMemcpyAsync((void*)d.tab, s->tabs.data(), sizeof(Tables) * s->n_sims,
+                             hipMemcpyHostToDevice, s->stream));
     Ctl c{};
     c.s[0] = StepState{0u, d.n_init, d.n_init, 0u};
     HIP_OK(s, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
+    s->host_next_id = n_init;
+    HIP_OK(s, hipMemcpyAsync(d.next_id, s->host_next_id.data(), 4 * s->n_sims,
+                             hipMemcpyHostToDevice, s->stream));
     // cell counts and both parities' tile sums start at zero
     HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ntiles * kScanTile * 4, s->stream));
     HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
     // claim slots are all-ones between steps (each step resets those it used)
     HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.capacity * 8, s->stream));
     launch_fill_records(d, s->stream);
-    if (place) launch_init(d, s->stream);
+    if (place)
+        for (uint32_t k = 0; k < s->n_sims; ++k) {
+            Dev dk = d;  // the placement of simulation k with its own tables
+            dk.tab = d.tab + k;
+            dk.n_init = n_init[k];
+            launch_init(dk, s->stream);
+        }
     HIP_OK(s, hipGetLastError());
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;
@@ -372,8 +449,9 @@ mabm_status live_counts(mabm_sim* s, std::vector<unsigned long long>& out, Ctl* 
 {
     launch_counts(s->dev, s->parity, s->stream);
     HIP_OK(s, hipGetLastError());
-    out.assign(kMaxSpecies, 0ull);
-    HIP_OK(s, hipMemcpyAsync(out.data(), s->dev.counts, kMaxSpecies * 8, hipMemcpyDeviceToHost, s->stream));
+    out.assign((size_t)kMaxSpecies * s->n_sims, 0ull);
+    HIP_OK(s, hipMemcpyAsync(out.data(), s->dev.counts, out.size() * 8, hipMemcpyDeviceToHost,
+                             s->stream));
     return sync_ctl(s, ctl);
 }
 
@@ -382,24 +460,44 @@ mabm_status live_counts(mabm_sim* s, std::vector<unsigned long long>& out, Ctl* 
 // ---------------------------------------------------------------------------
 extern "C" {
 
-size_t mabm_arena_bytes(const mabm_config* cfg, uint32_t n_species, uint32_t n_rules)
+}  // extern "C"
+
+namespace {
+
+// a batch's configurations must agree on everything but seed, volume size,
+// capacity and cell size
+bool batch_ok(const mabm_config* cs, uint32_t n, std::string& why)
 {
-    std::string why;
-    if (!config_ok(cfg, why) || n_species > MABM_MAX_SPECIES || n_rules > MABM_MAX_RULES) return 0;
-    return make_layout(*cfg).total;
+    if (!cs || n == 0 || n > kMaxSims) {
+        why = "a batch holds 1 to 65535 simulations";
+        return false;
+    }
+    for (uint32_t k = 0; k < n; ++k) {
+        if (!config_ok(&cs[k], why)) return false;
+        if (cs[k].geometry != cs[0].geometry || cs[k].dt_s != cs[0].dt_s ||
+            cs[k].flags != cs[0].flags) {
+            why = "batch configurations differ in geometry, dt_s or flags";
+            return false;
+        }
+    }
+    if (total_capacity(cs, n) > (1ull << 30)) {
+        why = "summed capacity of the batch above 2^30";
+        return false;
+    }
+    return true;
 }
 
-mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t arena_bytes,
-                            void* hip_stream, mabm_sim** out)
+mabm_status create_impl(const mabm_config* cs, uint32_t n, void* device_arena, size_t arena_bytes,
+                        void* hip_stream, mabm_sim** out)
 {
     if (!out) return MABM_E_INVALID;
     *out = nullptr;
     std::string why;
-    if (!config_ok(cfg, why)) {
+    if (!batch_ok(cs, n, why)) {
         g_create_error = why;
         return MABM_E_INVALID;
     }
-    Layout L = make_layout(*cfg);
+    Layout L = make_layout(cs, n);
     if (!device_arena || arena_bytes < L.total) {
         g_create_error = "arena smaller than mabm_arena_bytes()";
         return MABM_E_NOMEM;
@@ -410,7 +508,9 @@ mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t a
     }
     mabm_sim* s = new (std::nothrow) mabm_sim();
     if (!s) return MABM_E_NOMEM;
-    s->cfg = *cfg;
+    s->cfg = cs[0];
+    s->cfgs.assign(cs, cs + n);
+    s->n_sims = n;
     s->stream = (hipStream_t)hip_stream;
     s->arena = (uint8_t*)device_arena;
     s->arena_bytes = arena_bytes;
@@ -418,6 +518,36 @@ mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t a
     fill_dev(s);
     *out = s;
     return MABM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mabm_arena_bytes(const mabm_config* cfg, uint32_t n_species, uint32_t n_rules)
+{
+    return mabm_batch_arena_bytes(cfg, 1, n_species, n_rules);
+}
+
+size_t mabm_batch_arena_bytes(const mabm_config* cfgs, uint32_t n_sims, uint32_t n_species,
+                              uint32_t n_rules)
+{
+    std::string why;
+    if (!batch_ok(cfgs, n_sims, why) || n_species > MABM_MAX_SPECIES || n_rules > MABM_MAX_RULES)
+        return 0;
+    return make_layout(cfgs, n_sims).total;
+}
+
+mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t arena_bytes,
+                            void* hip_stream, mabm_sim** out)
+{
+    return create_impl(cfg, 1, device_arena, arena_bytes, hip_stream, out);
+}
+
+mabm_status mabm_create_batch(const mabm_config* cfgs, uint32_t n_sims, void* device_arena,
+                              size_t arena_bytes, void* hip_stream, mabm_sim** out)
+{
+    return create_impl(cfgs, n_sims, device_arena, arena_bytes, hip_stream, out);
 }
 
 mabm_status mabm_add_species(mabm_sim* s, const char* name, float D, uint32_t count, int32_t comp,
@@ -430,7 +560,18 @@ mabm_status mabm_add_species(mabm_sim* s, const char* name, float D, uint32_t co
     if (!(D >= 0.0f) || !std::isfinite(D)) return fail(s, MABM_E_INVALID, "diffusion must be finite and >= 0");
     if (comp < 0 || comp >= ncomp) return fail(s, MABM_E_INVALID, "compartment does not exist in this geometry");
     s->species.push_back({name ? name : "", D, count, comp});
+    s->sim_counts.emplace_back(s->n_sims, count);
     if (out_id) *out_id = (int32_t)s->species.size() - 1;
+    return MABM_OK;
+}
+
+mabm_status mabm_set_initial_counts(mabm_sim* s, int32_t species_id, const uint32_t* counts)
+{
+    if (!s || !counts) return MABM_E_INVALID;
+    if (s->finalized || s->failed) return fail(s, MABM_E_STATE, "initial counts after the model was finalized");
+    if (species_id < 0 || species_id >= (int32_t)s->species.size())
+        return fail(s, MABM_E_INVALID, "unknown species");
+    s->sim_counts[species_id].assign(counts, counts + s->n_sims);
     return MABM_OK;
 }
 
@@ -478,11 +619,13 @@ mabm_status mabm_add_rule(mabm_sim* s, const mabm_rule* r, int32_t* out_id)
             if (r->from_comp < 0 || r->to_comp < 0 || r->to_comp >= ncomp || r->to_comp == r->from_comp)
                 return fail(s, MABM_E_INVALID, "bad translocation compartments");
             if (r->product[1] != -1) return fail(s, MABM_E_INVALID, "TRANSLOCATE has one product");
-            const double rt = r->to_comp == 0
-                                  ? (double)s->cfg.inner_radius_um - (double)r->release_radius_um
-                                  : (double)s->cfg.inner_radius_um + (double)r->release_radius_um;
-            if (!(r->release_radius_um >= 1e-3f) || !(rt > 0.0) || !(rt < (double)s->cfg.outer_radius_um))
-                return fail(s, MABM_E_INVALID, "bad translocation offset");
+            for (const mabm_config& c : s->cfgs) {
+                const double rt = r->to_comp == 0
+                                      ? (double)c.inner_radius_um - (double)r->release_radius_um
+                                      : (double)c.inner_radius_um + (double)r->release_radius_um;
+                if (!(r->release_radius_um >= 1e-3f) || !(rt > 0.0) || !(rt < (double)c.outer_radius_um))
+                    return fail(s, MABM_E_INVALID, "bad translocation offset");
+            }
             break;
         }
         default:
@@ -577,7 +720,12 @@ mabm_status mabm_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t
     Ctl ctl{};
     st = live_counts(s, c, &ctl);
     if (st != MABM_OK) return st;
-    for (uint32_t k = 0; k < n_species; ++k) out[k] = k < (uint32_t)kMaxSpecies ? c[k] : 0;
+    for (uint32_t k = 0; k < n_species; ++k) {
+        uint64_t v = 0;
+        if (k < (uint32_t)kMaxSpecies)
+            for (uint32_t m = 0; m < s->n_sims; ++m) v += c[(size_t)m * kMaxSpecies + k];
+        out[k] = v;
+    }
     if (out_step) *out_step = ctl.s[s->parity].t;
     return MABM_OK;
 }
@@ -585,6 +733,7 @@ mabm_status mabm_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t
 mabm_status mabm_size(mabm_sim* s, uint32_t* n_live, uint32_t* next_id)
 {
     if (!s) return MABM_E_INVALID;
+    if (is_batch(s, "mabm_size")) return MABM_E_STATE;
     mabm_status st = finalize(s, true);
     if (st != MABM_OK) return st;
     if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
@@ -597,10 +746,15 @@ mabm_status mabm_size(mabm_sim* s, uint32_t* n_live, uint32_t* next_id)
     return MABM_OK;
 }
 
-mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* species, float* x,
-                        float* y, float* z, uint32_t* key, int32_t* event, uint32_t* partner)
+}  // extern "C"
+
+namespace {
+
+// live agents of simulation `sim` (a single simulation: 0), sorted by id
+mabm_status export_impl(mabm_sim* s, uint32_t sim, uint32_t capacity, uint32_t* id,
+                        uint8_t* species, float* x, float* y, float* z, uint32_t* key,
+                        int32_t* event, uint32_t* partner)
 {
-    if (!s) return MABM_E_INVALID;
     mabm_status st = finalize(s, true);
     if (st != MABM_OK) return st;
     if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
@@ -624,7 +778,7 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
     idx.reserve(n);
     for (uint32_t i = 0; i < n; ++i) {
         hs[i] = (uint8_t)(hr[i].w & 0xFFu);
-        if (hs[i] != kDead) idx.push_back(i);
+        if (hs[i] != kDead && (hr[i].w >> kMetaSimShift) == sim) idx.push_back(i);
     }
     if (idx.size() > capacity) return fail(s, MABM_E_INVALID, "export buffer smaller than the live agents");
     std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return hid[a] < hid[b]; });
@@ -643,10 +797,23 @@ mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* s
     return MABM_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+mabm_status mabm_export(mabm_sim* s, uint32_t capacity, uint32_t* id, uint8_t* species, float* x,
+                        float* y, float* z, uint32_t* key, int32_t* event, uint32_t* partner)
+{
+    if (!s) return MABM_E_INVALID;
+    if (is_batch(s, "mabm_export")) return MABM_E_STATE;
+    return export_impl(s, 0, capacity, id, species, x, y, z, key, event, partner);
+}
+
 mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8_t* sp,
                         const float* x, const float* y, const float* z, uint32_t next_id, uint32_t t)
 {
     if (!s) return MABM_E_INVALID;
+    if (is_batch(s, "mabm_import")) return MABM_E_STATE;
     if (s->finalized) return fail(s, MABM_E_STATE, "import after the model was finalized");
     if (n > s->cfg.capacity) return fail(s, MABM_E_CAPACITY, "import exceeds the capacity");
     const mabm_config& c = s->cfg;
@@ -716,6 +883,68 @@ mabm_status mabm_profile_read(mabm_sim* s, const char** names, uint64_t* launche
         if (launches) launches[k] = s->launches[k];
         if (total_ms) total_ms[k] = s->total_ms[k];
     }
+    return MABM_OK;
+}
+
+mabm_status mabm_batch_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t* out_step)
+{
+    if (!s || !out) return MABM_E_INVALID;
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    std::vector<unsigned long long> c;
+    Ctl ctl{};
+    st = live_counts(s, c, &ctl);
+    if (st != MABM_OK) return st;
+    for (uint32_t m = 0; m < s->n_sims; ++m)
+        for (uint32_t k = 0; k < n_species; ++k)
+            out[(size_t)m * n_species + k] =
+                k < (uint32_t)kMaxSpecies ? c[(size_t)m * kMaxSpecies + k] : 0;
+    if (out_step) *out_step = ctl.s[s->parity].t;
+    return MABM_OK;
+}
+
+mabm_status mabm_batch_size(mabm_sim* s, uint32_t sim, uint32_t* n_live, uint32_t* next_id)
+{
+    if (!s) return MABM_E_INVALID;
+    if (sim >= s->n_sims) return fail(s, MABM_E_INVALID, "simulation index out of range");
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    std::vector<unsigned long long> c;
+    Ctl ctl{};
+    st = live_counts(s, c, &ctl);
+    if (st != MABM_OK) return st;
+    if (n_live)
+        *n_live = (uint32_t)std::accumulate(c.begin() + (size_t)sim * kMaxSpecies,
+                                            c.begin() + (size_t)(sim + 1) * kMaxSpecies, 0ull);
+    if (next_id) {
+        if (s->n_sims == 1) {
+            *next_id = ctl.s[s->parity].next_id;
+        } else {
+            HIP_OK(s, hipMemcpy(next_id, s->dev.next_id + sim, 4, hipMemcpyDeviceToHost));
+        }
+    }
+    return MABM_OK;
+}
+
+mabm_status mabm_batch_export(mabm_sim* s, uint32_t sim, uint32_t capacity, uint32_t* id,
+                              uint8_t* species, float* x, float* y, float* z, uint32_t* key,
+                              int32_t* event, uint32_t* partner)
+{
+    if (!s) return MABM_E_INVALID;
+    if (sim >= s->n_sims) return fail(s, MABM_E_INVALID, "simulation index out of range");
+    return export_impl(s, sim, capacity, id, species, x, y, z, key, event, partner);
+}
+
+mabm_status mabm_batch_grid(mabm_sim* s, uint32_t sim, uint32_t* g, float* h)
+{
+    if (!s) return MABM_E_INVALID;
+    if (sim >= s->n_sims) return fail(s, MABM_E_INVALID, "simulation index out of range");
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (g) *g = s->sim_G[sim];
+    if (h) *h = s->sim_h[sim];
     return MABM_OK;
 }
 

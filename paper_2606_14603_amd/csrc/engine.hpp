@@ -15,10 +15,14 @@ constexpr int kMaxUni = 8;        // unimolecular rules per (species, compartmen
 constexpr uint8_t kDead = 0xFF;   // species byte of a consumed agent (hole)
 constexpr uint8_t kNoEvent = 0xFF;
 // An agent is a 16-byte record {x, y, z, meta} (position bits, then
-// species in bits 0-7 and this step's flags in bits 8-15) plus its id in a
-// separate array.
+// species in bits 0-7, this step's flags in bits 8-15 and, in a batch, the
+// index of the agent's simulation in bits 16-31) plus its id in a separate
+// array.
 constexpr uint32_t kMetaBusy = 1u << 8;     // had a unimolecular event this step
 constexpr uint32_t kMetaClaimer = 1u << 9;  // non-busy agent of a claiming species
+constexpr uint32_t kMetaSimShift = 16;
+constexpr uint32_t kMetaSimMask = 0xFFFF0000u;
+constexpr uint32_t kMaxSims = 65535;
 constexpr int kMetaSpeciesByte = 12;        // byte offset of the species in a record
 constexpr int kMetaFlagsByte = 13;          // byte offset of the flags in a record
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -60,6 +64,10 @@ struct Tables {
                            // coordinates over a 2^bits grid per axis
     uint32_t key0, key1;   // Philox key (seed low, high)
     uint32_t has_births, pad;
+    // position of this simulation in a batch (all zero for a single one):
+    // its index, its first cell in the batch's cell order, its first slot
+    // at placement
+    uint32_t sim, cell_base, slot_base, pad2;
     uint32_t init_end[kMaxSpecies];  // prefix sums of initial counts (placement)
     int32_t init_comp[kMaxSpecies];
     float sigma[kMaxSpecies];
@@ -93,7 +101,7 @@ struct Ctl {
 };
 
 struct Birth {
-    uint32_t parent, sp;
+    uint32_t parent, sp;  // sp: species, and the simulation index in bits 16-31
     float x, y, z;
 };
 
@@ -120,8 +128,10 @@ struct Dev {
     uint8_t* revent;
     uint32_t* rpartner;
     Birth* births;
-    unsigned long long* counts;  // kMaxSpecies
+    unsigned long long* counts;  // [n_sims][kMaxSpecies]
+    uint32_t* next_id;           // batch: per simulation, the next id to assign
     uint32_t capacity, ncells, ntiles, n_init;
+    uint32_t n_sims;             // 1: a single simulation; tab has n_sims entries
 };
 
 // kernel indices for per-kernel timing

@@ -83,6 +83,24 @@ __device__ __forceinline__ uint32_t run_add(uint32_t key, uint32_t* counter, uin
     return base + uint32_t(lane - head_lane);
 }
 
+// Runs f(u) once for every distinct simulation index u among the active
+// lanes, with u wave-uniform and only the lanes of simulation u active, so
+// that the simulation's tables are read with scalar loads.  Agents are
+// sorted by simulation, so nearly every wave takes one pass.
+template <class F>
+__device__ __forceinline__ void per_sim(uint32_t sim, F&& f)
+{
+    for (;;) {
+        const uint32_t u = __builtin_amdgcn_readfirstlane(sim);
+        if (sim == u) {
+            f(u);
+            break;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t sim_of(uint32_t meta) { return meta >> kMetaSimShift; }
+
 __device__ __forceinline__ uint32_t* tile_acc(const Dev& d, int p)
 {
     return d.tile_acc + size_t(p) * d.ntiles * kTileStride;
@@ -138,8 +156,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Dev d)
     }
     if (!ok) atomicOr(&d.ctl->err, kErrPlacement);
     const Agents A = d.a[0];
-    A.rec[i] = make_rec(x, y, z, uint32_t(s));
-    A.id[i] = i;
+    A.rec[T.slot_base + i] = make_rec(x, y, z, uint32_t(s) | (T.sim << kMetaSimShift));
+    A.id[T.slot_base + i] = i;
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_records(Dev d)
@@ -189,11 +207,11 @@ __device__ void release_offset(const Tables& T, const RuleDev& R, uint32_t id, u
     ux = uy = uz = 0.0f;
 }
 
-__device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent, int sp, float x,
-                                           float y, float z)
+__device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent, uint32_t sp_sim,
+                                           float x, float y, float z)
 {
     const uint32_t k = atomicAdd(&d.ctl->n_births[p], 1u);
-    if (k < kMaxBirthsPerStep) d.births[k] = Birth{parent, uint32_t(sp), x, y, z};
+    if (k < kMaxBirthsPerStep) d.births[k] = Birth{parent, sp_sim, x, y, z};
 }
 
 // ---------------------------------------------------------------------------
@@ -201,9 +219,116 @@ __device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent,
 // unimolecular part of O8, then the cell key of the moved position and the
 // agent's rank within its cell.
 // ---------------------------------------------------------------------------
+// One live agent's step up to its cell key (the body of move).
+template <bool B>
+__device__ __forceinline__ void move_agent(const Dev& d, const Tables& T, const Agents& A, int p,
+                                           int record, uint32_t i, uint32_t id, uint32_t t,
+                                           const uint4& r, uint32_t s, uint32_t& key)
+{
+    const float x = __uint_as_float(r.x), y = __uint_as_float(r.y), z = __uint_as_float(r.z);
+    const int c0 = compartment(T, x, y, z);
+    const U4 w = draw(T, id, t, kMove, 0u);
+
+    int ev = -1;
+    const int nu = T.uni_n[s][c0];
+    if (nu) {
+        const uint32_t wu = event_bits(w);
+        for (int j = 0; j < nu; ++j)
+            if (uint64_t(wu) < T.uni_thr[s][c0][j]) {
+                ev = T.uni_rule[s][c0][j];
+                break;
+            }
+    }
+
+    float z0, z1, z2;
+    normals3(w, z0, z1, z2);
+    const float sg = T.sigma[s];
+    float x1 = x + sg * z0, y1 = y + sg * z1, w1 = z + sg * z2;
+    if (T.geometry == kBox) {
+        x1 = wrap_box(T, x1);
+        y1 = wrap_box(T, y1);
+        w1 = wrap_box(T, w1);
+    } else {
+        const float n2 = sq3(x1, y1, w1);
+        bool reject = n2 > T.Rout2;
+        if (T.geometry == kNested && !reject && (n2 < T.Rin2 ? 0 : 1) != c0) reject = true;
+        if (reject) {
+            x1 = x;
+            y1 = y;
+            w1 = z;
+        }
+    }
+
+    uint32_t fs = s;
+    float fx = x1, fy = y1, fz = w1;
+    bool dies = false;
+    if (ev >= 0) {
+        const RuleDev& R = T.rule[ev];
+        float ux, uy, uz;
+        switch (R.placement) {
+        case kKeep:
+            if (R.p0 < 0) dies = true;
+            else fs = uint32_t(R.p0);
+            break;
+        case kTranslocate: {
+            const float n2 = sq3(x1, y1, w1);
+            if (n2 == 0.0f) {
+                fx = R.target_r;
+                fy = 0.0f;
+                fz = 0.0f;
+            } else {
+                const float f = R.target_r / __builtin_sqrtf(n2);
+                fx = x1 * f;
+                fy = y1 * f;
+                fz = w1 * f;
+            }
+            if (R.p0 >= 0) fs = uint32_t(R.p0);
+            break;
+        }
+        case kSplit: {
+            release_offset(T, R, id, t, x1, y1, w1, true, ux, uy, uz);
+            fs = uint32_t(R.p0);
+            fx = x1 + ux;
+            fy = y1 + uy;
+            fz = w1 + uz;
+            float cx = x1 - ux, cy = y1 - uy, cz = w1 - uz;
+            if (T.geometry == kBox) {
+                fx = wrap_box(T, fx);
+                fy = wrap_box(T, fy);
+                fz = wrap_box(T, fz);
+                cx = wrap_box(T, cx);
+                cy = wrap_box(T, cy);
+                cz = wrap_box(T, cz);
+            }
+            push_birth(d, p, id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz);
+            break;
+        }
+        default: {  // kEmit
+            release_offset(T, R, id, t, x1, y1, w1, false, ux, uy, uz);
+            if (R.p0 >= 0) fs = uint32_t(R.p0);
+            float cx = x1 + ux, cy = y1 + uy, cz = w1 + uz;
+            if (T.geometry == kBox) {
+                cx = wrap_box(T, cx);
+                cy = wrap_box(T, cy);
+                cz = wrap_box(T, cz);
+            }
+            push_birth(d, p, id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz);
+            break;
+        }
+        }
+    }
+    if (!dies) {
+        key = cell_of(T, x1, y1, w1);
+        if (B) key += T.cell_base;
+        A.rec[i] = make_rec(fx, fy, fz,
+                            fs | (ev >= 0 ? kMetaBusy : 0u) | (B ? r.w & kMetaSimMask : 0u));
+        if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
+    }
+}
+
+template <bool B>
 __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
 {
-    const Tables& T = *d.tab;
     const uint32_t n = d.ctl->s[p].n_slots;
     const uint32_t t = d.ctl->s[p].t;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -224,103 +349,12 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
     }
     const uint32_t s = r.w & 0xFFu;
     if (s != kDead) {
-        const float x = __uint_as_float(r.x), y = __uint_as_float(r.y), z = __uint_as_float(r.z);
-        const int c0 = compartment(T, x, y, z);
-        const U4 w = draw(T, id, t, kMove, 0u);
-
-        int ev = -1;
-        const int nu = T.uni_n[s][c0];
-        if (nu) {
-            const uint32_t wu = event_bits(w);
-            for (int j = 0; j < nu; ++j)
-                if (uint64_t(wu) < T.uni_thr[s][c0][j]) {
-                    ev = T.uni_rule[s][c0][j];
-                    break;
-                }
-        }
-
-        float z0, z1, z2;
-        normals3(w, z0, z1, z2);
-        const float sg = T.sigma[s];
-        float x1 = x + sg * z0, y1 = y + sg * z1, w1 = z + sg * z2;
-        if (T.geometry == kBox) {
-            x1 = wrap_box(T, x1);
-            y1 = wrap_box(T, y1);
-            w1 = wrap_box(T, w1);
-        } else {
-            const float n2 = sq3(x1, y1, w1);
-            bool reject = n2 > T.Rout2;
-            if (T.geometry == kNested && !reject && (n2 < T.Rin2 ? 0 : 1) != c0) reject = true;
-            if (reject) {
-                x1 = x;
-                y1 = y;
-                w1 = z;
-            }
-        }
-
-        uint32_t fs = s;
-        float fx = x1, fy = y1, fz = w1;
-        bool dies = false;
-        if (ev >= 0) {
-            const RuleDev& R = T.rule[ev];
-            float ux, uy, uz;
-            switch (R.placement) {
-            case kKeep:
-                if (R.p0 < 0) dies = true;
-                else fs = uint32_t(R.p0);
-                break;
-            case kTranslocate: {
-                const float n2 = sq3(x1, y1, w1);
-                if (n2 == 0.0f) {
-                    fx = R.target_r;
-                    fy = 0.0f;
-                    fz = 0.0f;
-                } else {
-                    const float f = R.target_r / __builtin_sqrtf(n2);
-                    fx = x1 * f;
-                    fy = y1 * f;
-                    fz = w1 * f;
-                }
-                if (R.p0 >= 0) fs = uint32_t(R.p0);
-                break;
-            }
-            case kSplit: {
-                release_offset(T, R, id, t, x1, y1, w1, true, ux, uy, uz);
-                fs = uint32_t(R.p0);
-                fx = x1 + ux;
-                fy = y1 + uy;
-                fz = w1 + uz;
-                float cx = x1 - ux, cy = y1 - uy, cz = w1 - uz;
-                if (T.geometry == kBox) {
-                    fx = wrap_box(T, fx);
-                    fy = wrap_box(T, fy);
-                    fz = wrap_box(T, fz);
-                    cx = wrap_box(T, cx);
-                    cy = wrap_box(T, cy);
-                    cz = wrap_box(T, cz);
-                }
-                push_birth(d, p, id, R.p1, cx, cy, cz);
-                break;
-            }
-            default: {  // kEmit
-                release_offset(T, R, id, t, x1, y1, w1, false, ux, uy, uz);
-                if (R.p0 >= 0) fs = uint32_t(R.p0);
-                float cx = x1 + ux, cy = y1 + uy, cz = w1 + uz;
-                if (T.geometry == kBox) {
-                    cx = wrap_box(T, cx);
-                    cy = wrap_box(T, cy);
-                    cz = wrap_box(T, cz);
-                }
-                push_birth(d, p, id, R.p1, cx, cy, cz);
-                break;
-            }
-            }
-        }
-        if (!dies) {
-            key = cell_of(T, x1, y1, w1);
-            A.rec[i] = make_rec(fx, fy, fz, fs | (ev >= 0 ? kMetaBusy : 0u));
-            if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
-        }
+        if (B)
+            per_sim(sim_of(r.w), [&](uint32_t u) {
+                move_agent<true>(d, d.tab[u], A, p, record, i, id, t, r, s, key);
+            });
+        else
+            move_agent<false>(d, *d.tab, A, p, record, i, id, t, r, s, key);
     }
     // rank within the cell, and the per-tile sums the scan starts from
     const uint32_t rank = run_add(key, d.cell_count, 1u);
@@ -425,9 +459,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRankLds = 1024;  // births ranked from LDS; more read from L2
 
+template <bool B>
 __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
 {
-    __shared__ uint32_t skey[kRankLds];
+    __shared__ uint32_t skey[kRankLds], ssim[kRankLds];
     Ctl* ctl = d.ctl;
     const StepState cur = ctl->s[p];
     const uint32_t nbin = ctl->n_binned;
@@ -440,25 +475,62 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
         err = kErrCapacity;
         nb = 0;
     }
+    // a birth's order key: its parent id, and in a batch its simulation
+    // first (slots follow (simulation, parent id); ids are per simulation)
     const bool in_lds = nb <= kRankLds;
     if (in_lds)
-        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) skey[k] = d.births[k].parent;
+        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
+            const Birth bb = d.births[k];
+            skey[k] = bb.parent;
+            ssim[k] = bb.sp >> kMetaSimShift;
+        }
     __syncthreads();
     const Agents A = d.a[p ^ 1];
     for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
         const Birth bb = d.births[k];
-        uint32_t r = 0;
-        if (in_lds)
-            for (uint32_t m = 0; m < nb; ++m) r += skey[m] < bb.parent ? 1u : 0u;
-        else
-            for (uint32_t m = 0; m < nb; ++m) r += d.births[m].parent < bb.parent ? 1u : 0u;
+        const uint32_t sim = bb.sp >> kMetaSimShift;
+        uint32_t r = 0, rs = 0;  // rank among all births, among the simulation's births
+        for (uint32_t m = 0; m < nb; ++m) {
+            uint32_t pm, sm;
+            if (in_lds) {
+                pm = skey[m];
+                sm = ssim[m];
+            } else {
+                const Birth o = d.births[m];
+                pm = o.parent;
+                sm = o.sp >> kMetaSimShift;
+            }
+            if (B) {
+                r += (sm < sim || (sm == sim && pm < bb.parent)) ? 1u : 0u;
+                rs += (sm == sim && pm < bb.parent) ? 1u : 0u;
+            } else {
+                r += pm < bb.parent ? 1u : 0u;
+            }
+        }
         const uint32_t j = nbin + r;
         A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp);
-        A.id[j] = cur.next_id + r;
+        A.id[j] = B ? d.next_id[sim] + rs : cur.next_id + r;
         if (record) {
             d.rkey[j] = kNone;
             d.revent[j] = kNoEvent;
             d.rpartner[j] = kNone;
+        }
+    }
+    if (B) {
+        // every id is assigned; each simulation's counter advances by its
+        // number of births, added by its last-ranked birth
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
+            const Birth bb = d.births[k];
+            const uint32_t sim = bb.sp >> kMetaSimShift;
+            uint32_t rs = 0, ns = 0;
+            for (uint32_t m = 0; m < nb; ++m) {
+                const uint32_t sm = in_lds ? ssim[m] : d.births[m].sp >> kMetaSimShift;
+                const uint32_t pm = in_lds ? skey[m] : d.births[m].parent;
+                ns += sm == sim ? 1u : 0u;
+                rs += (sm == sim && pm < bb.parent) ? 1u : 0u;
+            }
+            if (rs + 1u == ns) d.next_id[sim] += ns;
         }
     }
     if (threadIdx.x == 0) {
@@ -478,10 +550,11 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
 // (non-busy agent of a claiming species) is set in the record and in the
 // one-byte array the propose chunks scan.
 // ---------------------------------------------------------------------------
+template <bool B>
 __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 {
     if (blockIdx.x == gridDim.x - 1) {
-        births_and_bookkeeping(d, p, record);
+        births_and_bookkeeping<B>(d, p, record);
         return;
     }
     const Tables& T = *d.tab;
@@ -492,15 +565,20 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     if (kr.x == kNone) return;
     const uint32_t j = d.cell_start[kr.x] + kr.y;
     const Agents A = d.a[p];
-    const Agents B = d.a[p ^ 1];
+    const Agents O = d.a[p ^ 1];
     uint4 r = A.rec[i];
     const bool claim = !(r.w & kMetaBusy) && T.claimer[r.w & 0xFFu];
     if (claim) r.w |= kMetaClaimer;
-    B.rec[j] = r;
-    B.id[j] = A.id[i];
+    O.rec[j] = r;
+    O.id[j] = A.id[i];
     d.sclaim[j] = claim ? 1 : 0;
     if (record) {
-        d.rkey[j] = linear_cell(T, kr.x);
+        if (B) {
+            const Tables& Ts = d.tab[sim_of(r.w)];
+            d.rkey[j] = linear_cell(Ts, kr.x - Ts.cell_base);
+        } else {
+            d.rkey[j] = linear_cell(T, kr.x);
+        }
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
     }
@@ -609,6 +687,92 @@ __device__ __forceinline__ void reduce_best(Best& b, int width)
     }
 }
 
+// O7 search for one claimer j (record rj) by its subgroup of `width` lanes
+// (lane li scans stencil cells li and li + width), then lane 0's Bernoulli
+// draw and handshake keys.
+template <bool B>
+__device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, const PairLds& P,
+                                               const Agents& A, uint32_t t, uint32_t j,
+                                               const uint4& rj, int li, int width, int ncell,
+                                               uint32_t* plocal, uint32_t* nprop)
+{
+    const int G = int(T.G);
+    const bool periodic = T.geometry == kBox;
+    const uint32_t s = rj.w & 0xFFu;
+    const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
+    const int comp = compartment(T, x, y, z);
+    const float pp[3] = {x, y, z};
+    int c[3];
+    float f[3];
+    for (int a = 0; a < 3; ++a) {
+        c[a] = int(cell_coord(T, pp[a]));
+        f[a] = (pp[a] - T.lo) * T.inv_h - float(c[a]);
+    }
+    // candidate range of stencil cell m (empty outside the grid)
+    auto range = [&](int m, uint32_t& lo, uint32_t& hi) {
+        lo = hi = 0;
+        if (m >= ncell) return;
+        int cc[3];
+        for (int a = 0; a < 3; ++a) {
+            int v;
+            if (T.stencil8) {
+                // the neighbour on the side of the cell the point is nearer
+                const int bit = (m >> a) & 1;
+                v = c[a] + bit * (f[a] < 0.5f ? -1 : 1);
+            } else {
+                const int o = a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9);
+                v = c[a] + o - 1;
+            }
+            if (periodic) v = (v + G) % G;
+            else if (v < 0 || v >= G) return;
+            cc[a] = v;
+        }
+        uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
+        if (B) cell += T.cell_base;
+        lo = d.cell_start[cell];
+        hi = d.cell_start[cell + 1];
+    };
+    uint32_t k0, e0, k1, e1;
+    range(li, k0, e0);
+    range(li + width, k1, e1);
+    Best b{kNone, 0u, 0.0f, -1};
+    // up to two candidates of each cell per round, all four records
+    // requested together
+    while (k0 < e0 || k1 < e1) {
+        const bool a0 = k0 < e0, a1 = k0 + 1 < e0, b0 = k1 < e1, b1 = k1 + 1 < e1;
+        uint4 r0{}, r1{}, r2{}, r3{};
+        if (a0) r0 = A.rec[k0];
+        if (a1) r1 = A.rec[k0 + 1];
+        if (b0) r2 = A.rec[k1];
+        if (b1) r3 = A.rec[k1 + 1];
+        if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, b);
+        if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, b);
+        if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, b);
+        if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, b);
+        k0 += 2;
+        k1 += 2;
+    }
+    reduce_best(b, width);
+    if (li == 0) {
+        uint32_t out = kNone;
+        if (b.idx != kNone) {
+            const uint32_t ida = A.id[j];
+            const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
+            if (uint64_t(w) < T.rule[b.rule].thr) {
+                const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
+                const unsigned long long pr =
+                    (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
+                atomicMin(&d.slot[j], pr | b.id);
+                atomicMin(&d.slot[b.idx], pr | ida);
+                out = b.idx;
+                plocal[atomicAdd(nprop, 1u)] = j;
+            }
+        }
+        d.prop[j] = out;
+    }
+}
+
+template <bool B>
 __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 {
     __shared__ uint32_t list[kPChunk];
@@ -641,9 +805,8 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
     const uint32_t nl = compact_claimers(word, first, last, list, &count);
-    const int G = int(T.G);
-    const bool periodic = T.geometry == kBox;
     // a subgroup of `width` lanes per claimer, two stencil cells per lane
+    // (the stencil is the same for every simulation of a batch)
     const int width = T.stencil8 ? 4 : 16;
     const int ncell = T.stencil8 ? 8 : 27;
     const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
@@ -651,77 +814,12 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
         const uint32_t j = list[q];
         const uint4 rj = A.rec[j];
-        const uint32_t s = rj.w & 0xFFu;
-        const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
-        const int comp = compartment(T, x, y, z);
-        const float pp[3] = {x, y, z};
-        int c[3];
-        float f[3];
-        for (int a = 0; a < 3; ++a) {
-            c[a] = int(cell_coord(T, pp[a]));
-            f[a] = (pp[a] - T.lo) * T.inv_h - float(c[a]);
-        }
-        // candidate range of stencil cell m (empty outside the grid)
-        auto range = [&](int m, uint32_t& lo, uint32_t& hi) {
-            lo = hi = 0;
-            if (m >= ncell) return;
-            int cc[3];
-            for (int a = 0; a < 3; ++a) {
-                int v;
-                if (T.stencil8) {
-                    // the neighbour on the side of the cell the point is nearer
-                    const int bit = (m >> a) & 1;
-                    v = c[a] + bit * (f[a] < 0.5f ? -1 : 1);
-                } else {
-                    const int o = a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9);
-                    v = c[a] + o - 1;
-                }
-                if (periodic) v = (v + G) % G;
-                else if (v < 0 || v >= G) return;
-                cc[a] = v;
-            }
-            const uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
-            lo = d.cell_start[cell];
-            hi = d.cell_start[cell + 1];
-        };
-        uint32_t k0, e0, k1, e1;
-        range(li, k0, e0);
-        range(li + width, k1, e1);
-        Best b{kNone, 0u, 0.0f, -1};
-        // up to two candidates of each cell per round, all four records
-        // requested together
-        while (k0 < e0 || k1 < e1) {
-            const bool a0 = k0 < e0, a1 = k0 + 1 < e0, b0 = k1 < e1, b1 = k1 + 1 < e1;
-            uint4 r0{}, r1{}, r2{}, r3{};
-            if (a0) r0 = A.rec[k0];
-            if (a1) r1 = A.rec[k0 + 1];
-            if (b0) r2 = A.rec[k1];
-            if (b1) r3 = A.rec[k1 + 1];
-            if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, b);
-            if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, b);
-            if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, b);
-            if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, b);
-            k0 += 2;
-            k1 += 2;
-        }
-        reduce_best(b, width);
-        if (li == 0) {
-            uint32_t out = kNone;
-            if (b.idx != kNone) {
-                const uint32_t ida = A.id[j];
-                const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
-                if (uint64_t(w) < T.rule[b.rule].thr) {
-                    const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
-                    const unsigned long long pr =
-                        (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
-                    atomicMin(&d.slot[j], pr | b.id);
-                    atomicMin(&d.slot[b.idx], pr | ida);
-                    out = b.idx;
-                    plocal[atomicAdd(&nprop, 1u)] = j;
-                }
-            }
-            d.prop[j] = out;
-        }
+        if (B)
+            per_sim(sim_of(rj.w), [&](uint32_t u) {
+                search_claimer<true>(d, d.tab[u], P, A, t, j, rj, li, width, ncell, plocal, &nprop);
+            });
+        else
+            search_claimer<false>(d, T, P, A, t, j, rj, li, width, ncell, plocal, &nprop);
     }
     // the workgroup's proposers join the step's proposer list (one global
     // atomic per workgroup that has any)
@@ -739,6 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
 // Species are written as single bytes, so the flag byte of the same record,
 // which another thread may be testing, is never rewritten.
 // ---------------------------------------------------------------------------
+template <bool B>
 __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record)
 {
     __shared__ uint32_t s_holes;
@@ -755,7 +854,9 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record)
         const uint32_t b = d.prop[j];
         const uint32_t ida = A.id[j], idb = A.id[b];
         const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
-        const unsigned long long pr = (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
+        // the pair's simulation gives the Philox key
+        const Tables& Tk = B ? d.tab[sim_of(A.rec[j].w)] : T;
+        const unsigned long long pr = (unsigned long long)draw(Tk, lo_id, t, kPrio, hi_id).w0 << 32;
         if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) continue;
         // b proposed too only if it carries the claimer flag (its prop is
         // then this step's); a mutual pair fires once, from the lower id.
@@ -794,9 +895,41 @@ __global__ void __launch_bounds__(kBlock) k_counts(Dev d, int cur)
         atomicAdd(&d.counts[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
+// per (simulation, species) counts of a batch: one workgroup per 256 slots,
+// the LDS histogram holding the simulation of the workgroup's first slot and
+// the next one (agents are sorted by simulation); any other goes to memory
+__global__ void __launch_bounds__(kBlock) k_counts_batch(Dev d, int cur)
+{
+    __shared__ uint32_t h[2][kMaxSpecies];
+    __shared__ uint32_t base;
+    const uint32_t n = d.ctl->s[cur].n_slots;
+    const uint32_t first = blockIdx.x * kBlock;
+    if (first >= n) return;
+    const uint4* rec = d.a[cur].rec;
+    if (threadIdx.x < 2 * kMaxSpecies) h[threadIdx.x / kMaxSpecies][threadIdx.x % kMaxSpecies] = 0;
+    if (threadIdx.x == 0) base = sim_of(rec[first].w);
+    __syncthreads();
+    const uint32_t i = first + threadIdx.x;
+    if (i < n) {
+        const uint32_t w = rec[i].w;
+        const uint32_t s = w & 0xFFu, sim = sim_of(w);
+        if (s < uint32_t(kMaxSpecies)) {
+            if (sim - base < 2u) atomicAdd(&h[sim - base][s], 1u);
+            else atomicAdd(&d.counts[size_t(sim) * kMaxSpecies + s], 1ull);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxSpecies) {
+        const uint32_t k = threadIdx.x / kMaxSpecies, s = threadIdx.x % kMaxSpecies;
+        if (h[k][s] && base + k < d.n_sims)
+            atomicAdd(&d.counts[size_t(base + k) * kMaxSpecies + s], (unsigned long long)h[k][s]);
+    }
+}
+
 __global__ void k_zero_counts(Dev d)
 {
-    if (threadIdx.x < kMaxSpecies) d.counts[threadIdx.x] = 0ull;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < d.n_sims * uint32_t(kMaxSpecies)) d.counts[i] = 0ull;
 }
 
 }  // namespace
@@ -825,9 +958,12 @@ static inline void go(K kernel, unsigned grid, unsigned block, hipStream_t s, co
     hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, ev.start, ev.stop, 0, args...);
 }
 
+// the batch variants of the agent kernels (template argument true) resolve
+// each agent's simulation; a single simulation takes the plain ones
 void launch_move(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
-    go(k_move, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
+    if (d.n_sims > 1) go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
+    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
 }
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
@@ -836,22 +972,29 @@ void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
     // one workgroup per 256 slots, plus the births/bookkeeping workgroup
-    go(k_scatter, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
+    if (d.n_sims > 1) go(k_scatter<true>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
+    else go(k_scatter<false>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
 }
 void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
-    go(k_propose, chunks_for(d.capacity), kBlock, s, ev, d, p);
+    if (d.n_sims > 1) go(k_propose<true>, chunks_for(d.capacity), kBlock, s, ev, d, p);
+    else go(k_propose<false>, chunks_for(d.capacity), kBlock, s, ev, d, p);
 }
 void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
     // a fixed grid strides over the step's proposer list
     unsigned nb = blocks_for(d.capacity);
     if (nb > kFinishBlocks) nb = kFinishBlocks;
-    go(k_finish, nb, kBlock, s, ev, d, p, record);
+    if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record);
+    else go(k_finish<false>, nb, kBlock, s, ev, d, p, record);
 }
 void launch_counts(const Dev& d, int cur, hipStream_t s)
 {
-    k_zero_counts<<<1, 64, 0, s>>>(d);
+    k_zero_counts<<<blocks_for(d.n_sims * uint32_t(kMaxSpecies)), kBlock, 0, s>>>(d);
+    if (d.n_sims > 1) {
+        k_counts_batch<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur);
+        return;
+    }
     unsigned nb = blocks_for(d.capacity);
     if (nb > 2048) nb = 2048;
     k_counts<<<nb, kBlock, 0, s>>>(d, cur);
