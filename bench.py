@@ -115,6 +115,71 @@ def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:
             "sample": f"{model.name}, {n0} agents, first {steps} steps, single-threaded C oracle"}
 
 
+def _bits(e: dict) -> dict:
+    return {k: (v.view("uint32") if v.dtype.kind == "f" else v) for k, v in e.items()}
+
+
+def run_sweep(args, torch, mabm, W) -> dict:
+    """The dose x replicate sweep: every simulation for its whole horizon,
+    once as one batch and once one at a time through the single-simulation
+    path (a sample of simulations, extrapolated), with the sampled
+    simulations' final states compared bit for bit."""
+    models = W.c4_sweep(n_reps=args.sweep_reps, steps=args.sweep_steps)
+    n, steps = len(models), args.sweep_steps
+    agents = sum(m.n_agents for m in models)
+    # warm the code objects on a small batch first
+    warm = mabm.Batch(models[:2])
+    warm.step(3)
+    warm.counts()
+    del warm
+    batch = mabm.Batch(models)
+    batch.grid()  # finalize: tables, placement
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    u0 = batch.agent_updates()
+    e0.record(batch.stream)
+    batch.step(steps)
+    e1.record(batch.stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1)
+    updates = batch.agent_updates() - u0
+    sample = list(range(0, n, max(1, n // args.sweep_sample)))[:args.sweep_sample]
+    ms_serial, same = 0.0, True
+    for k in sample:
+        sim = mabm.Sim(models[k])
+        sim.grid()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(sim.stream)
+        sim.step(steps)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        ms_serial += a.elapsed_time(b)
+        ge, be = _bits(sim.export()), _bits(batch.export(k))
+        for f in ("id", "species", "x", "y", "z"):
+            same = same and bool((ge[f] == be[f]).all()) and len(ge[f]) == len(be[f])
+        sim.close()
+    ms_serial_all = ms_serial * n / len(sample)
+    value = n / (ms_batch * 1e-3)
+    serial = n / (ms_serial_all * 1e-3)
+    return {
+        "metric": METRIC, "value": value, "unit": "sims/s", "n_gpus": 1, "steps": steps,
+        "warmup": 0, "ms_per_step": ms_batch / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c4_sweep: {len(models) // args.sweep_reps} doses x "
+                               f"{args.sweep_reps} replicates of c2_mapk, 20k-200k agents each, "
+                               f"{steps} steps", "sims": n, "agents": agents},
+        "batched": {"ms": ms_batch, "agent_updates_per_s": updates / (ms_batch * 1e-3)},
+        "serial": {"value": serial, "unit": "sims/s", "ms_extrapolated": ms_serial_all,
+                   "sample": f"{len(sample)} of {n} simulations run one at a time, "
+                             f"{ms_serial:.1f} ms, scaled by {n}/{len(sample)}"},
+        "speedup_vs_serial": value / serial,
+        "bit_identical_sample": same,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +193,13 @@ def main() -> int:
                     help="replay each step as a captured HIP graph (default: direct launches)")
     ap.add_argument("--cell-um", type=float, default=0.0,
                     help="spatial-hash cell size (0: the library's choice)")
+    ap.add_argument("--workload", choices=("c2", "c4"), default="c2",
+                    help="c2: the 2M-agent step (agent-updates/s); c4: the batched "
+                         "dose x replicate sweep (sims/s vs serial)")
+    ap.add_argument("--sweep-reps", type=int, default=64, help="c4: replicates per dose")
+    ap.add_argument("--sweep-steps", type=int, default=2000, help="c4: steps per simulation")
+    ap.add_argument("--sweep-sample", type=int, default=16,
+                    help="c4: simulations run one at a time for the serial baseline")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run 4 plain device copies of this many MiB (untimed), so a "
                          "counter profile of this command holds a copy kernel of known bytes")
@@ -141,8 +213,11 @@ def main() -> int:
     import paper_2606_14603_amd as mabm
     import workloads as W
 
-    model = W.c2(args.agents)
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        print(json.dumps(run_sweep(args, torch, mabm, W)), flush=True)
+        return 0
+    model = W.c2(args.agents)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -80,7 +80,7 @@ bool config_ok(const mabm_config* c, std::string& why)
 struct Layout {
     size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_acc, slot,
         prop, plist, rkey, revent, rpartner, births, counts, next_id, total;
-    uint32_t ncells, ntiles;
+    uint32_t ncells, ntiles, tile_shift;
 };
 
 // Layout of one simulation (n = 1) or of a batch of n: agent arrays sized
@@ -102,7 +102,11 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
         cells += (size_t)1 << (3 * morton_bits(grid_from_config(cs[k])));
     }
     L.ncells = (uint32_t)cells;
-    L.ntiles = (uint32_t)((cells + kScanTile - 1) / kScanTile);
+    L.tile_shift = 0;
+    while (((cells + ((size_t)kScanTile << L.tile_shift) - 1) >> (kScanTileLog + L.tile_shift)) >
+           kMaxScanTiles)
+        ++L.tile_shift;
+    L.ntiles = (uint32_t)((cells + ((size_t)kScanTile << L.tile_shift) - 1) >> (kScanTileLog + L.tile_shift));
     L.ctl = take(sizeof(Ctl));
     L.tab = take(sizeof(Tables) * n);
     for (int b = 0; b < 2; ++b) {
@@ -112,7 +116,7 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.kr = take(cap * 8);
     L.event = take(cap);
     L.sclaim = take((cap + kClaimChunk - 1) / kClaimChunk * kClaimChunk);
-    const size_t padded = (size_t)L.ntiles * kScanTile;  // whole scan tiles
+    const size_t padded = (size_t)L.ntiles << (kScanTileLog + L.tile_shift);  // whole scan tiles
     L.cell_count = take(padded * 4);
     L.cell_start = take((padded + 1) * 4);
     L.tile_acc = take((size_t)2 * L.ntiles * kTileStride * 4);
@@ -154,6 +158,7 @@ struct mabm_sim {
     std::vector<uint32_t> sim_G;
     std::vector<float> sim_h;
     std::vector<uint32_t> host_next_id;  // staging for the per-simulation id counters
+    uint64_t steps_done = 0;             // steps enqueued since finalize
     hipStream_t stream = nullptr;
     uint8_t* arena = nullptr;
     size_t arena_bytes = 0;
@@ -395,7 +400,9 @@ mabm_status finalize(mabm_sim* s, bool place)
     Dev& d = s->dev;
     const Tables& last = s->tabs.back();
     d.ncells = last.cell_base + (1u << (3 * last.morton_bits));
-    d.ntiles = (d.ncells + kScanTile - 1) / kScanTile;
+    d.tile_shift = s->lay.tile_shift;
+    d.ntiles = (uint32_t)(((size_t)d.ncells + ((size_t)kScanTile << d.tile_shift) - 1) >>
+                          (kScanTileLog + d.tile_shift));
     // agents placed: every simulation's initial counts, one after another
     std::vector<uint32_t> n_init(s->n_sims);
     uint32_t total = 0;
@@ -413,7 +420,8 @@ mabm_status finalize(mabm_sim* s, bool place)
     HIP_OK(s, hipMemcpyAsync(d.next_id, s->host_next_id.data(), 4 * s->n_sims,
                              hipMemcpyHostToDevice, s->stream));
     // cell counts and both parities' tile sums start at zero
-    HIP_OK(s, hipMemsetAsync(d.cell_count, 0, (size_t)d.ntiles * kScanTile * 4, s->stream));
+    HIP_OK(s, hipMemsetAsync(d.cell_count, 0, ((size_t)d.ntiles << (kScanTileLog + d.tile_shift)) * 4,
+                             s->stream));
     HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
     // claim slots are all-ones between steps (each step resets those it used)
     HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.capacity * 8, s->stream));
@@ -705,6 +713,7 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
             enqueue_step(s, cur);
         }
         s->parity = cur ^ 1;
+        ++s->steps_done;
     }
     HIP_OK(s, hipGetLastError());
     return MABM_OK;
@@ -761,22 +770,48 @@ mabm_status export_impl(mabm_sim* s, uint32_t sim, uint32_t capacity, uint32_t* 
     Ctl ctl{};
     st = sync_ctl(s, &ctl);
     if (st != MABM_OK) return st;
-    const uint32_t n = ctl.s[s->parity].n_slots;
+    const uint32_t n_slots = ctl.s[s->parity].n_slots;
     const Agents& A = s->dev.a[s->parity];
+    // slot ranges that can hold the simulation's agents: all slots for a
+    // single simulation; in a batch, its initial block before any step, and
+    // after one its cells' run of the cell-sorted array plus the last step's
+    // births, appended after the binned agents
+    std::vector<std::pair<uint32_t, uint32_t>> ranges;
+    if (s->n_sims == 1) {
+        ranges.push_back({0u, n_slots});
+    } else if (s->steps_done == 0) {
+        const Tables& T = s->tabs[sim];
+        ranges.push_back({T.slot_base, T.slot_base + T.init_end[T.ns - 1]});
+    } else {
+        const Tables& T = s->tabs[sim];
+        uint32_t cs[2];
+        HIP_OK(s, hipMemcpyAsync(&cs[0], s->dev.cell_start + T.cell_base, 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(&cs[1], s->dev.cell_start + T.cell_base + (1u << (3 * T.morton_bits)), 4,
+                                 hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipStreamSynchronize(s->stream));
+        ranges.push_back({cs[0], cs[1]});
+        if (n_slots > ctl.n_binned) ranges.push_back({ctl.n_binned, n_slots});
+    }
+    size_t n = 0;
+    for (auto& r : ranges) n += r.second - r.first;
     std::vector<uint4> hr(n);
     std::vector<uint32_t> hid(n), hk(n), hp(n);
     std::vector<uint8_t> hs(n), he(n);
-    if (n) {
-        HIP_OK(s, hipMemcpyAsync(hr.data(), A.rec, (size_t)n * 16, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hid.data(), A.id, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hk.data(), s->dev.rkey, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(he.data(), s->dev.revent, n, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hp.data(), s->dev.rpartner, n * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipStreamSynchronize(s->stream));
+    size_t off = 0;
+    for (auto& r : ranges) {
+        const size_t m = r.second - r.first, b = r.first;
+        if (!m) continue;
+        HIP_OK(s, hipMemcpyAsync(hr.data() + off, A.rec + b, m * 16, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hid.data() + off, A.id + b, m * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hk.data() + off, s->dev.rkey + b, m * 4, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(he.data() + off, s->dev.revent + b, m, hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(s, hipMemcpyAsync(hp.data() + off, s->dev.rpartner + b, m * 4, hipMemcpyDeviceToHost, s->stream));
+        off += m;
     }
+    HIP_OK(s, hipStreamSynchronize(s->stream));
     std::vector<uint32_t> idx;
     idx.reserve(n);
-    for (uint32_t i = 0; i < n; ++i) {
+    for (uint32_t i = 0; i < (uint32_t)n; ++i) {
         hs[i] = (uint8_t)(hr[i].w & 0xFFu);
         if (hs[i] != kDead && (hr[i].w >> kMetaSimShift) == sim) idx.push_back(i);
     }

@@ -30,7 +30,13 @@ constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
 constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
 constexpr int kScanItems = 8;                 // cells per thread in the scan
 constexpr int kScanThreads = 256;
-constexpr int kScanTile = kScanItems * kScanThreads;
+constexpr int kScanTile = kScanItems * kScanThreads;  // cells per scan pass of a workgroup
+constexpr int kScanTileLog = 11;
+static_assert(kScanTile == 1 << kScanTileLog, "scan tile is a power of two");
+// A scan tile (one workgroup of the scan, one counter of the per-tile sums)
+// spans 2^tile_shift passes of kScanTile cells, the smallest power that
+// keeps the number of tiles at most kMaxScanTiles.
+constexpr uint32_t kMaxScanTiles = 1024;
 // sorted agents per workgroup of the neighbour search; the claimer-flag
 // array is padded to a whole number of these
 constexpr uint32_t kClaimChunk = 1024;
@@ -131,6 +137,7 @@ struct Dev {
     unsigned long long* counts;  // [n_sims][kMaxSpecies]
     uint32_t* next_id;           // batch: per simulation, the next id to assign
     uint32_t capacity, ncells, ntiles, n_init;
+    uint32_t tile_shift;         // a scan tile is kScanTile << tile_shift cells
     uint32_t n_sims;             // 1: a single simulation; tab has n_sims entries
 };
 

@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
     }
     // rank within the cell, and the per-tile sums the scan starts from
     const uint32_t rank = run_add(key, d.cell_count, 1u);
-    run_add(key == kNone ? kNone : key / uint32_t(kScanTile), tile_acc(d, p), kTileStride);
+    run_add(key == kNone ? kNone : key >> (kScanTileLog + d.tile_shift), tile_acc(d, p), kTileStride);
     if (i < n) d.kr[i] = uint2{key, rank};
 }
 
@@ -403,49 +403,68 @@ __device__ __forceinline__ uint32_t block_excl_scan_sum(uint32_t v, uint32_t r, 
     }
     *total_v = tot;
     *total_r = totr;
+    __syncthreads();  // wsum may be rewritten by the next call
     return off + inc - v;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 {
     const uint32_t tile = blockIdx.x;
-    // the tile's own counts are requested before the preceding tiles' sums,
-    // so both loads are in flight together
-    const uint32_t base = tile * kScanTile + threadIdx.x * kScanItems;
+    const uint32_t npass = 1u << d.tile_shift;
     constexpr int kVec = kScanItems / 4;
-    uint4* cnt4 = reinterpret_cast<uint4*>(d.cell_count + base);
+    uint4* cnt4 = reinterpret_cast<uint4*>(d.cell_count + (size_t(tile) << (kScanTileLog + d.tile_shift)) +
+                                           threadIdx.x * kScanItems);
+    uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + (size_t(tile) << (kScanTileLog + d.tile_shift)) +
+                                          threadIdx.x * kScanItems);
+    constexpr uint32_t kPassVec = kScanTile / 4;  // uint4 per pass
+    // the first pass's counts are requested before the preceding tiles'
+    // sums, so both loads are in flight together
     uint4 v[kVec];
 #pragma unroll
     for (int k = 0; k < kVec; ++k) v[k] = cnt4[k];
     const uint32_t* acc = tile_acc(d, p);
     uint32_t before = 0;
     for (uint32_t k = threadIdx.x; k < tile; k += kScanThreads) before += acc[size_t(k) * kTileStride];
-    uint32_t sum = 0;
+    uint32_t base = 0;  // cells before this pass
+    for (uint32_t pass = 0; pass < npass; ++pass) {
+        // the next pass's counts are requested before this pass is scanned
+        uint4 nx[kVec];
+        if (pass + 1 < npass) {
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) sum += v[k].x + v[k].y + v[k].z + v[k].w;
-    uint32_t prefix, total;
-    uint32_t run = block_excl_scan_sum(sum, before, &total, &prefix);
-    run += prefix;
-    uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + base);
+            for (int k = 0; k < kVec; ++k) nx[k] = cnt4[(pass + 1) * kPassVec + k];
+        }
+        uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) {
-        uint4 o;
-        o.x = run;
-        run += v[k].x;
-        o.y = run;
-        run += v[k].y;
-        o.z = run;
-        run += v[k].z;
-        o.w = run;
-        run += v[k].w;
-        st4[k] = o;
-        cnt4[k] = uint4{0u, 0u, 0u, 0u};
+        for (int k = 0; k < kVec; ++k) sum += v[k].x + v[k].y + v[k].z + v[k].w;
+        uint32_t total, prefix;
+        uint32_t run = block_excl_scan_sum(sum, pass == 0 ? before : 0u, &total, &prefix);
+        if (pass == 0) base = prefix;
+        run += base;
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) {
+            uint4 o;
+            o.x = run;
+            run += v[k].x;
+            o.y = run;
+            run += v[k].y;
+            o.z = run;
+            run += v[k].z;
+            o.w = run;
+            run += v[k].w;
+            st4[pass * kPassVec + k] = o;
+            cnt4[pass * kPassVec + k] = uint4{0u, 0u, 0u, 0u};
+        }
+        base += total;
+        if (pass + 1 < npass) {
+#pragma unroll
+            for (int k = 0; k < kVec; ++k) v[k] = nx[k];
+        }
     }
     if (threadIdx.x == 0) {
         tile_acc(d, p ^ 1)[size_t(tile) * kTileStride] = 0u;
         if (tile == d.ntiles - 1) {
-            d.cell_start[d.ntiles * kScanTile] = prefix + total;
-            d.ctl->n_binned = prefix + total;
+            d.cell_start[size_t(d.ntiles) << (kScanTileLog + d.tile_shift)] = base;
+            d.ctl->n_binned = base;
         }
     }
 }
