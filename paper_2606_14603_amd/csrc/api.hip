@@ -167,7 +167,8 @@ struct mabm_sim {
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};  // one captured step per parity
+    // captured steps, per starting parity: one step, and kGraphSteps steps
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     int parity = 0;
     uint32_t G = 0;
     float h = 0.0f;
@@ -676,14 +677,20 @@ void enqueue_step(mabm_sim* s, int p)
     }
 }
 
-// capture one step of each parity as a graph on the caller's stream
-mabm_status capture(mabm_sim* s, int cur)
+// Capture `steps` consecutive steps starting at parity cur as one graph on
+// the caller's stream (kernel nodes only: the step has no memset or copy).
+// Long runs replay the multi-step graph, so the host issues one launch per
+// kGraphSteps steps; that matters for small simulations, whose steps take
+// about as long to enqueue as to run.
+constexpr uint32_t kGraphSteps = 16;
+
+mabm_status capture(mabm_sim* s, int cur, uint32_t steps, hipGraphExec_t* out)
 {
     hipGraph_t g = nullptr;
     HIP_OK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    enqueue_step(s, cur);
+    for (uint32_t k = 0; k < steps; ++k) enqueue_step(s, cur ^ int(k & 1u));
     HIP_OK(s, hipStreamEndCapture(s->stream, &g));
-    const hipError_t e = hipGraphInstantiate(&s->graph[cur], g, nullptr, nullptr, 0);
+    const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(s, e, "hipGraphInstantiate");
     return MABM_OK;
@@ -701,19 +708,25 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
     // graphs need a capturable (non-null) stream; per-kernel timing records
     // events between the kernels, so it launches them directly
     const bool graphs = s->stream != nullptr && !s->prof && !(s->cfg.flags & MABM_FLAG_NO_GRAPH);
-    for (uint32_t k = 0; k < n_steps; ++k) {
+    uint32_t k = 0;
+    while (k < n_steps) {
         const int cur = s->parity;
+        uint32_t m = 1;
         if (graphs) {
-            if (!s->graph[cur]) {
-                st = capture(s, cur);
+            const int kind = n_steps - k >= kGraphSteps ? 1 : 0;
+            m = kind ? kGraphSteps : 1u;
+            hipGraphExec_t& g = s->graph[cur][kind];
+            if (!g) {
+                st = capture(s, cur, m, &g);
                 if (st != MABM_OK) return st;
             }
-            HIP_OK(s, hipGraphLaunch(s->graph[cur], s->stream));
+            HIP_OK(s, hipGraphLaunch(g, s->stream));
         } else {
             enqueue_step(s, cur);
         }
-        s->parity = cur ^ 1;
-        ++s->steps_done;
+        s->parity = cur ^ int(m & 1u);
+        s->steps_done += m;
+        k += m;
     }
     HIP_OK(s, hipGetLastError());
     return MABM_OK;
@@ -999,8 +1012,9 @@ mabm_status mabm_destroy_sim(mabm_sim* s)
 {
     if (!s) return MABM_E_INVALID;
     (void)hipStreamSynchronize(s->stream);
-    for (hipGraphExec_t& g : s->graph)
-        if (g) (void)hipGraphExecDestroy(g);
+    for (auto& per_parity : s->graph)
+        for (hipGraphExec_t& g : per_parity)
+            if (g) (void)hipGraphExecDestroy(g);
     for (EventPair& p : s->pool) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

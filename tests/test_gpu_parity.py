@@ -172,3 +172,22 @@ def test_nested_dense_membrane_contacts():
     agents = [(i, int(s), float(q[0]), float(q[1]), float(q[2]))
               for i, (s, q) in enumerate(zip(rng.integers(0, 2, n), p))]
     run_pair(m, [1, 2, 10, 40], importer=_import_pair(agents, n))
+
+
+def test_graph_replay_matches_direct_launches():
+    # Steps replayed from captured graphs (single steps and 16-step graphs of
+    # both starting parities) against direct launches, checked after every
+    # run of steps, with eager queries between the replays.
+    import paper_2606_14603_amd as mabm
+    for m in (W.c3(20_000, seed=42, n_genes=300), W.c2(30_000, seed=9)):
+        g = mabm.Sim(m, record=True, graphs=True)
+        e = mabm.Sim(m, record=True, graphs=False)
+        done = 0
+        for n in (37, 1, 16, 50, 3, 33):
+            g.step(n)
+            e.step(n)
+            done += n
+            assert_same(g.export(), e.export(), f"{m.name} graphs t={done}")
+            assert np.array_equal(g.counts()[0], e.counts()[0])
+            assert g.agent_updates() == e.agent_updates()
+        say(f"[graphs] {m.name} ok at t={done}")
