@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -180,6 +182,50 @@ def run_sweep(args, torch, mabm, W) -> dict:
     }
 
 
+def run_serving(args, torch, mabm, W) -> dict:
+    """The request stream: each request a model of its own (a random closed
+    subset of the cascade's rules, 50k-1M agents, 200-2000 steps).  The
+    FIFO server (one request at a time) is first run on all requests
+    arriving at once to measure its capacity; Poisson arrivals at 0.7 x that
+    rate are then served FIFO and by the concurrent server, which keeps
+    every admitted simulation resident and advances them on streams of their
+    own.  Admission: arrival order, while the summed arenas fit the budget."""
+    from paper_2606_14603_amd import serve
+    models = W.c5_requests(args.serve_requests, seed=0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free) if args.serve_budget_gb <= 0 else int(args.serve_budget_gb * 2**30)
+    # load the code objects and the graph path once
+    serve.Server(budget, max_active=2).run(W.c5_requests(2, seed=99, n_max=60_000, h_max=300),
+                                           [0.0, 0.0])
+    fifo = serve.Server(budget, max_active=1, chunk=args.serve_chunk)
+    cap = serve.summarize(fifo.run(models, np.zeros(len(models))))
+    rate = 0.7 * cap["sims_per_s"]
+    arrivals = W.poisson_arrivals(len(models), rate, seed=0)
+    res_fifo = fifo.run(models, arrivals)
+    conc = serve.Server(budget, max_active=args.serve_active, chunk=args.serve_chunk)
+    cap_conc = serve.summarize(conc.run(models, np.zeros(len(models))))
+    res_conc = conc.run(models, arrivals)
+    s_fifo, s_conc = serve.summarize(res_fifo), serve.summarize(res_conc)
+    by_name = {r.name: r.counts for r in res_fifo}
+    same = all(np.array_equal(by_name[r.name], r.counts) for r in res_conc)
+    return {
+        "metric": METRIC, "value": s_conc["sims_per_s"], "unit": "sims/s", "n_gpus": 1,
+        "steps": int(sum(m.steps for m in models)), "warmup": 2,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c5_requests: {len(models)} requests, random closed subsets of "
+                               f"the cascade's rules, 50k-1M agents, 200-2000 steps, Poisson "
+                               f"arrivals at 0.7 x the FIFO capacity",
+                   "arrival_rate_per_s": rate, "budget_bytes": budget,
+                   "chunk_steps": args.serve_chunk, "max_active": args.serve_active},
+        "p50_s": s_conc["p50_s"], "p99_s": s_conc["p99_s"],
+        "concurrent": s_conc, "fifo": s_fifo, "fifo_capacity": cap,
+        "concurrent_capacity": cap_conc,
+        "capacity_ratio": cap_conc["sims_per_s"] / cap["sims_per_s"],
+        "identical_results": same,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,9 +239,15 @@ def main() -> int:
                     help="replay each step as a captured HIP graph (default: direct launches)")
     ap.add_argument("--cell-um", type=float, default=0.0,
                     help="spatial-hash cell size (0: the library's choice)")
-    ap.add_argument("--workload", choices=("c2", "c4"), default="c2",
+    ap.add_argument("--workload", choices=("c2", "c4", "c5"), default="c2",
                     help="c2: the 2M-agent step (agent-updates/s); c4: the batched "
-                         "dose x replicate sweep (sims/s vs serial)")
+                         "dose x replicate sweep (sims/s vs serial); c5: the serving loop "
+                         "(p50/p99 latency, sims/s vs FIFO)")
+    ap.add_argument("--serve-requests", type=int, default=256, help="c5: requests")
+    ap.add_argument("--serve-chunk", type=int, default=256, help="c5: steps per turn")
+    ap.add_argument("--serve-active", type=int, default=64, help="c5: simulations admitted at once")
+    ap.add_argument("--serve-budget-gb", type=float, default=0.0,
+                    help="c5: HBM budget for admitted arenas (0: 85%% of free memory)")
     ap.add_argument("--sweep-reps", type=int, default=64, help="c4: replicates per dose")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="c4: steps per simulation")
     ap.add_argument("--sweep-sample", type=int, default=16,
@@ -216,6 +268,9 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "c4":
         print(json.dumps(run_sweep(args, torch, mabm, W)), flush=True)
+        return 0
+    if args.workload == "c5":
+        print(json.dumps(run_serving(args, torch, mabm, W)), flush=True)
         return 0
     model = W.c2(args.agents)
     if args.copy_calib_mb:

@@ -229,6 +229,56 @@ def c3(n_total: int = 5_000_000, seed: int = 0, steps: int = 10_000, n_genes: in
 # --------------------------------------------------------------------------
 # C4: dose x replicate sweep of scaled copies of C2
 # --------------------------------------------------------------------------
+def c5_request(k: int, rng: np.random.Generator, n_min: int, n_max: int, h_min: int,
+               h_max: int) -> Model:
+    """One serving request: a random non-empty subset of C2's contact rules,
+    closed under its species (every C2 rule, contact or degradation, whose
+    reactants and products all lie in the subset's species is included), its
+    species renumbered 0.. in C2 order, counts from a random positive ratio
+    vector scaled to a log-uniform size, a uniform horizon, seed k; C2's
+    density in a sphere."""
+    full = c2_rules()
+    bim = [r for r in full if r.kind == BIMOL]
+    while True:
+        pick = [r for r in bim if rng.random() < 0.5]
+        if pick:
+            break
+    used = sorted({s for r in pick for s in (*r.reactants, *r.products) if s >= 0})
+    while True:  # closure under the species in use
+        rules = [r for r in full if all(s < 0 or s in used for s in (*r.reactants, *r.products))]
+        grown = sorted(set(used) | {s for r in rules for s in (*r.reactants, *r.products) if s >= 0})
+        if grown == used:
+            break
+        used = grown
+    remap = {s: i for i, s in enumerate(used)}
+    n_total = int(math.exp(rng.uniform(math.log(n_min), math.log(n_max))))
+    w = rng.uniform(0.05, 1.0, len(used))
+    counts = np.floor(w / w.sum() * n_total).astype(np.int64)
+    counts[np.argmax(counts)] += n_total - int(counts.sum())
+    sp = [Species(C2_SPECIES[s], C2_D[s], int(c)) for s, c in zip(used, counts)]
+    rr = [replace(r, reactants=tuple(remap.get(s, -1) if s >= 0 else -1 for s in r.reactants),
+                  products=tuple(remap.get(s, -1) if s >= 0 else -1 for s in r.products))
+          for r in rules]
+    horizon = int(rng.integers(h_min, h_max + 1))
+    radius = 5.0 * (n_total / 2_000_000) ** (1.0 / 3.0)
+    return Model(f"c5_req{k}", SPHERE, 1e-6, k, sp, rr, outer_radius_um=radius,
+                 capacity=n_total, steps=horizon)
+
+
+def c5_requests(n: int = 256, seed: int = 0, n_min: int = 50_000, n_max: int = 1_000_000,
+                h_min: int = 200, h_max: int = 2000) -> List[Model]:
+    """A stream of n serving requests (numpy seed ``seed``), each a model of
+    its own from ``c5_request``; ``steps`` is the request's horizon."""
+    rng = np.random.default_rng(seed)
+    return [c5_request(k, rng, n_min, n_max, h_min, h_max) for k in range(n)]
+
+
+def poisson_arrivals(n: int, rate_per_s: float, seed: int = 0) -> np.ndarray:
+    """Arrival times (s) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, n))
+
+
 def c4_sweep(n_doses: int = 16, n_reps: int = 64, n_min: int = 20_000, n_max: int = 200_000,
              steps: int = 2000, size_seed: int = 0) -> List[Model]:
     """16 inhibitor doses log-spaced over 3 decades below the top-dose
