@@ -232,6 +232,27 @@ mabm_status mabm_batch_export(mabm_sim* sim, uint32_t sim_index, uint32_t capaci
 mabm_status mabm_batch_grid(mabm_sim* sim, uint32_t sim_index, uint32_t* cells_per_axis,
                             float* cell_um);
 
+/* Counts over time without host synchronisation (Sec. 2: species are
+ * monitored against concentration thresholds within time windows; Sec. 3.2
+ * names step-wise host-device synchronisation and periodic output among the
+ * original simulator's costs).  While every > 0, after each step whose
+ * number since the first step is a multiple of every, the library appends
+ * one entry to a ring in the caller's device memory (device_ring, entries x
+ * mabm_ring_entry_bytes(sim) bytes, 8-byte aligned, borrowed until the ring
+ * is switched off with every = 0); a full ring overwrites its oldest entry.
+ * An entry is uint64 words: the step counter, then for every simulation of
+ * the handle (one unless it is a batch) MABM_MAX_SPECIES species counts.
+ * Recording splits graph replays at entry steps; results do not change. */
+size_t mabm_ring_entry_bytes(const mabm_sim* sim);
+mabm_status mabm_counts_ring(mabm_sim* sim, void* device_ring, uint32_t entries, uint32_t every);
+
+/* Copy the newest min(recorded, entries, max_entries) ring entries, oldest
+ * first, to out (max_entries x mabm_ring_entry_bytes bytes); *n_recorded
+ * receives the number of entries recorded since the ring was set.
+ * Synchronises the stream. */
+mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
+                           uint64_t* n_recorded);
+
 /* Per-kernel timing: while enabled (1), each step kernel is dispatched with
  * a pair of HIP events that the dispatch itself stamps at the kernel's start
  * and end, so the time is the kernel's own duration; steps then run as

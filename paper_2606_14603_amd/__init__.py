@@ -88,6 +88,10 @@ def lib() -> ctypes.CDLL:
         L.mabm_batch_size.argtypes = [P, c.c_uint32, P, P]
         L.mabm_batch_export.argtypes = [P, c.c_uint32, c.c_uint32, P, P, P, P, P, P, P, P]
         L.mabm_batch_grid.argtypes = [P, c.c_uint32, c.POINTER(c.c_uint32), c.POINTER(c.c_float)]
+        L.mabm_ring_entry_bytes.restype = c.c_size_t
+        L.mabm_ring_entry_bytes.argtypes = [P]
+        L.mabm_counts_ring.argtypes = [P, P, c.c_uint32, c.c_uint32]
+        L.mabm_ring_read.argtypes = [P, P, c.c_uint32, P]
         L.mabm_last_error.restype = c.c_char_p
         L.mabm_last_error.argtypes = [P]
         for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
@@ -95,7 +99,7 @@ def lib() -> ctypes.CDLL:
                      "mabm_profile", "mabm_profile_read", "mabm_agent_updates",
                      "mabm_destroy_sim", "mabm_create_batch", "mabm_set_initial_counts",
                      "mabm_batch_counts", "mabm_batch_size", "mabm_batch_export",
-                     "mabm_batch_grid"):
+                     "mabm_batch_grid", "mabm_counts_ring", "mabm_ring_read"):
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -231,6 +235,32 @@ class Sim:
                                           _ptr(launches), _ptr(ms)))
         return {(names[k] or b"kernel%d" % k).decode(): (int(launches[k]), float(ms[k]))
                 for k in range(N_KERNELS)}
+
+    def record_counts(self, every: int, entries: int = 4096):
+        """Append the live counts to a device ring every ``every`` steps
+        (0 stops); the ring holds the newest ``entries`` entries."""
+        import torch
+        L = lib()
+        if every <= 0:
+            self._chk(L.mabm_counts_ring(self._h, None, 0, 0))
+            self._ring = None
+            return
+        words = int(L.mabm_ring_entry_bytes(self._h)) // 8
+        self._ring = torch.zeros(entries * words, dtype=torch.int64, device=self.arena.device)
+        self._ring_words, self._ring_entries = words, entries
+        self._chk(L.mabm_counts_ring(self._h, ctypes.c_void_p(self._ring.data_ptr()), entries,
+                                     int(every)))
+
+    def ring(self):
+        """(steps, counts): the recorded entries, oldest first; counts has
+        shape (entries, simulations, species)."""
+        n = np.zeros(1, np.uint64)
+        buf = np.zeros(self._ring_entries * self._ring_words, np.uint64)
+        self._chk(lib().mabm_ring_read(self._h, _ptr(buf), self._ring_entries, _ptr(n)))
+        m = int(min(n[0], self._ring_entries))
+        e = buf[:m * self._ring_words].reshape(m, self._ring_words)
+        sims = (self._ring_words - 1) // 64
+        return e[:, 0].copy(), e[:, 1:].reshape(m, sims, 64)[:, :, :self.n_species].copy()
 
     def agent_updates(self) -> int:
         out = np.zeros(1, np.uint64)

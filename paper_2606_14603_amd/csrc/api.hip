@@ -159,6 +159,10 @@ struct mabm_sim {
     std::vector<float> sim_h;
     std::vector<uint32_t> host_next_id;  // staging for the per-simulation id counters
     uint64_t steps_done = 0;             // steps enqueued since finalize
+    // counts ring (caller's device memory): entries of ring_words u64
+    unsigned long long* ring = nullptr;
+    uint32_t ring_entries = 0, ring_every = 0;
+    uint64_t ring_recorded = 0;
     hipStream_t stream = nullptr;
     uint8_t* arena = nullptr;
     size_t arena_bytes = 0;
@@ -189,6 +193,10 @@ mabm_status fail(mabm_sim* s, mabm_status code, const std::string& msg)
     s->err = msg;
     return code;
 }
+
+// u64 words of a counts-ring entry: the step counter, then the counts of
+// every (simulation, species) pair, kMaxSpecies per simulation
+size_t ring_words(const mabm_sim* s) { return 1 + (size_t)s->n_sims * kMaxSpecies; }
 
 bool is_batch(mabm_sim* s, const char* call)
 {
@@ -712,8 +720,11 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
     while (k < n_steps) {
         const int cur = s->parity;
         uint32_t m = 1;
+        // steps until the next counts-ring entry (a graph never spans one)
+        const uint64_t until_rec =
+            s->ring_every ? s->ring_every - s->steps_done % s->ring_every : ~0ull;
         if (graphs) {
-            const int kind = n_steps - k >= kGraphSteps ? 1 : 0;
+            const int kind = (n_steps - k >= kGraphSteps && until_rec >= kGraphSteps) ? 1 : 0;
             m = kind ? kGraphSteps : 1u;
             hipGraphExec_t& g = s->graph[cur][kind];
             if (!g) {
@@ -727,6 +738,12 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
         s->parity = cur ^ int(m & 1u);
         s->steps_done += m;
         k += m;
+        if (s->ring_every && s->steps_done % s->ring_every == 0) {
+            unsigned long long* e =
+                s->ring + (s->ring_recorded % s->ring_entries) * ring_words(s);
+            launch_counts(s->dev, s->parity, s->stream, e + 1, e);
+            ++s->ring_recorded;
+        }
     }
     HIP_OK(s, hipGetLastError());
     return MABM_OK;
@@ -993,6 +1010,36 @@ mabm_status mabm_batch_grid(mabm_sim* s, uint32_t sim, uint32_t* g, float* h)
     if (st != MABM_OK) return st;
     if (g) *g = s->sim_G[sim];
     if (h) *h = s->sim_h[sim];
+    return MABM_OK;
+}
+
+size_t mabm_ring_entry_bytes(const mabm_sim* s) { return s ? 8 * ring_words(s) : 0; }
+
+mabm_status mabm_counts_ring(mabm_sim* s, void* device_ring, uint32_t entries, uint32_t every)
+{
+    if (!s) return MABM_E_INVALID;
+    if (every && (!device_ring || entries == 0 || (uintptr_t)device_ring % 8 != 0))
+        return fail(s, MABM_E_INVALID, "counts ring needs an 8-byte aligned buffer of >= 1 entry");
+    s->ring = every ? (unsigned long long*)device_ring : nullptr;
+    s->ring_entries = every ? entries : 0;
+    s->ring_every = every;
+    s->ring_recorded = 0;
+    return MABM_OK;
+}
+
+mabm_status mabm_ring_read(mabm_sim* s, uint64_t* out, uint32_t max_entries, uint64_t* n_recorded)
+{
+    if (!s) return MABM_E_INVALID;
+    if (n_recorded) *n_recorded = s->ring_recorded;
+    if (!s->ring || !out || max_entries == 0) return MABM_OK;
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    const uint64_t held = std::min<uint64_t>(s->ring_recorded, s->ring_entries);
+    const uint64_t n = std::min<uint64_t>(held, max_entries);
+    const size_t w = ring_words(s);
+    for (uint64_t k = 0; k < n; ++k) {  // the last n entries, oldest first
+        const uint64_t idx = (s->ring_recorded - n + k) % s->ring_entries;
+        HIP_OK(s, hipMemcpy(out + k * w, s->ring + idx * w, w * 8, hipMemcpyDeviceToHost));
+    }
     return MABM_OK;
 }
 

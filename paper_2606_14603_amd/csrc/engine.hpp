@@ -160,7 +160,10 @@ void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
 void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
-void launch_counts(const Dev& d, int cur, hipStream_t s);
+// per-(simulation, species) live counts into d.counts, or into dst (same
+// layout) with the step counter in *tslot (a counts-ring entry)
+void launch_counts(const Dev& d, int cur, hipStream_t s, unsigned long long* dst = nullptr,
+                   unsigned long long* tslot = nullptr);
 void launch_fill_records(const Dev& d, hipStream_t s);
 
 }  // namespace mabm

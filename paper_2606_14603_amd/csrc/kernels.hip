@@ -945,10 +945,12 @@ __global__ void __launch_bounds__(kBlock) k_counts_batch(Dev d, int cur)
     }
 }
 
-__global__ void k_zero_counts(Dev d)
+// clears the counts; a counts-ring entry also gets the step counter
+__global__ void k_zero_counts(Dev d, int cur, unsigned long long* tslot)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < d.n_sims * uint32_t(kMaxSpecies)) d.counts[i] = 0ull;
+    if (tslot && i == 0) *tslot = d.ctl->s[cur].t;
 }
 
 }  // namespace
@@ -1007,9 +1009,12 @@ void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents
     if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record);
     else go(k_finish<false>, nb, kBlock, s, ev, d, p, record);
 }
-void launch_counts(const Dev& d, int cur, hipStream_t s)
+void launch_counts(const Dev& d0, int cur, hipStream_t s, unsigned long long* dst,
+                   unsigned long long* tslot)
 {
-    k_zero_counts<<<blocks_for(d.n_sims * uint32_t(kMaxSpecies)), kBlock, 0, s>>>(d);
+    Dev d = d0;
+    if (dst) d.counts = dst;
+    k_zero_counts<<<blocks_for(d.n_sims * uint32_t(kMaxSpecies)), kBlock, 0, s>>>(d, cur, tslot);
     if (d.n_sims > 1) {
         k_counts_batch<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur);
         return;

@@ -1,0 +1,87 @@
+"""Counts over time from the device counts ring: every entry equals the
+oracle's counts at that step (graph replay and direct launches, ring
+wrap-around, batches), and a model loaded from a model file runs bit for
+bit like the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from parity import run_pair, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14603_amd as mabm
+    mabm.lib()
+
+
+def _oracle_series(m, every, total):
+    o = oracle.OracleSim(m)
+    out = []
+    for t in range(every, total + 1, every):
+        o.step(every)
+        c, tt = o.counts()
+        assert tt == t
+        out.append(c)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_ring_matches_oracle_counts(graphs):
+    import paper_2606_14603_amd as mabm
+    m = W.c3(12_000, seed=12, n_genes=200)
+    want = _oracle_series(m, 7, 140)
+    g = mabm.Sim(m, graphs=graphs)
+    g.record_counts(7, entries=64)
+    for n in (37, 1, 62, 40):
+        g.step(n)
+    steps, counts = g.ring()
+    assert list(steps) == list(range(7, 141, 7))
+    assert np.array_equal(counts[:, 0, :], want)
+    # a ring of 4 keeps the newest 4 entries
+    h = mabm.Sim(m, graphs=graphs)
+    h.record_counts(7, entries=4)
+    h.step(140)
+    steps, counts = h.ring()
+    assert list(steps) == [119, 126, 133, 140]
+    assert np.array_equal(counts[:, 0, :], want[-4:])
+    say(f"[ring] graphs={graphs} ok")
+
+
+def test_ring_of_a_batch():
+    import paper_2606_14603_amd as mabm
+    models = [W.c2(5000, seed=1), W.c2(9000, seed=2, inhibitor_fraction=0.1)]
+    b = mabm.Batch(models)
+    b.record_counts(10, entries=8)
+    b.step(50)
+    steps, counts = b.ring()
+    assert list(steps) == [10, 20, 30, 40, 50]
+    for k, m in enumerate(models):
+        assert np.array_equal(counts[:, k, :], _oracle_series(m, 10, 50))
+
+
+def test_model_file_runs_like_the_oracle():
+    from paper_2606_14603_amd import model_io
+    doc = {"name": "file", "geometry": {"kind": "nested", "radius_um": 1.0, "inner_radius_um": 0.5},
+           "dt_s": 1e-6, "seed": 4, "steps": 30,
+           "species": [{"name": "K", "mw_kda": 60.0, "concentration_M": 4e-6},
+                       {"name": "S", "mw_kda": 40.0, "concentration_M": 2e-5,
+                        "compartment": "nucleus"},
+                       {"name": "pS", "mw_kda": 40.0, "count": 0, "compartment": "nucleus"}],
+           "reactions": [{"reactants": ["K", "S"], "products": ["K", "pS"], "radius_nm": 12,
+                          "probability": 0.5},
+                         {"reactants": ["K"], "products": ["K"], "placement": "translocate",
+                          "from": "cytosol", "to": "nucleus", "release_nm": 5,
+                          "probability": 0.01},
+                         {"reactants": ["K"], "products": ["K"], "placement": "translocate",
+                          "from": "nucleus", "to": "cytosol", "release_nm": 5,
+                          "probability": 0.01},
+                         {"reactants": ["pS"], "products": ["S"], "kcat_per_s": 500.0}]}
+    m = model_io.load_model(doc)
+    run_pair(m, [1, 10, 30])

@@ -1,0 +1,114 @@
+"""Host-side model tooling: model files, molecular-weight-derived diffusion,
+concentration-derived counts, the consistency checks and threshold
+monitoring (CPU only)."""
+import copy
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_14603_amd import model_io as mio
+from paper_2606_14603_amd import monitor
+
+
+def doc():
+    return {
+        "name": "toy",
+        "geometry": {"kind": "sphere", "radius_um": 0.5},
+        "dt_s": 1e-6, "seed": 3, "steps": 20,
+        "species": [
+            {"name": "E", "class": "active", "mw_kda": 50.0, "concentration_M": 2e-6,
+             "partners": ["S"]},
+            {"name": "S", "class": "inactive", "mw_kda": 40.0, "concentration_M": 8e-6,
+             "partners": ["E"]},
+            {"name": "ES", "class": "inhibited", "diffusion_um2_s": 20.0, "count": 0},
+            {"name": "P", "class": "inactive", "mw_kda": 40.0, "count": 0},
+        ],
+        "reactions": [
+            {"reactants": ["E", "S"], "products": ["ES", None], "radius_nm": 10,
+             "probability": 0.5},
+            {"reactants": ["ES"], "products": ["E", "P"], "placement": "split",
+             "release_nm": 5, "kcat_per_s": 2000.0},
+        ],
+    }
+
+
+def test_radius_matches_the_protein_volume_rule():
+    # Erickson's minimal radius of a protein sphere, 0.066 M^(1/3) nm (M in
+    # Da) at 1.37 g/cm^3, rescaled to the 1.35 g/cm^3 used here
+    for kda in (10.0, 50.0, 150.0, 1000.0):
+        want = 0.066 * (kda * 1e3) ** (1 / 3) * (1.37 / 1.35) ** (1 / 3)
+        assert abs(mio.radius_nm(kda) - want) / want < 0.01
+
+
+def test_stokes_einstein_scaling_and_value():
+    d50 = mio.stokes_einstein_um2_s(50.0)
+    # D r = k T / (6 pi eta): a sphere of radius 1 nm in water at 37 C
+    # diffuses at 328 um^2/s
+    assert abs(d50 * mio.radius_nm(50.0) - 328.6) < 1.0
+    assert abs(mio.stokes_einstein_um2_s(400.0) / d50 - 0.5) < 1e-9  # M^(-1/3)
+    # doubling the viscosity halves D; D grows with temperature as T
+    assert abs(mio.stokes_einstein_um2_s(50.0, viscosity_pa_s=2 * mio.WATER_37C_PA_S) - d50 / 2) < 1e-9
+    assert abs(mio.stokes_einstein_um2_s(50.0, temperature_k=2 * 310.15) - 2 * d50) < 1e-9
+
+
+def test_counts_and_kcat():
+    assert mio.count_from_concentration(1e-6, 1.0) == 602  # 1 uM in 1 um^3 (1 fL)
+    v = 4 / 3 * math.pi * 0.5 ** 3
+    m = mio.load_model(doc())
+    assert m.species[0].count == round(2e-6 * v * 1e-15 * mio.N_A)
+    assert m.species[1].count == round(8e-6 * v * 1e-15 * mio.N_A)
+    p = m.rules[1].prob_per_step
+    # survival over n steps equals the exponential waiting time's
+    assert abs((1 - p) ** 500 - math.exp(-2000.0 * 1e-6 * 500)) < 1e-12
+    assert m.rules[0].radius_um == pytest.approx(0.010)
+    assert m.species[2].diffusion_um2_s == 20.0
+
+
+def test_loaded_model_runs_on_the_oracle():
+    m = mio.load_model(doc())
+    o = oracle.OracleSim(m)
+    o.step(m.steps)
+    c, t = o.counts()
+    assert t == m.steps
+    # E + ES and S + ES + P are conserved by binding and release
+    assert c[0] + c[2] == m.species[0].count
+    assert c[1] + c[2] + c[3] == m.species[1].count
+
+
+@pytest.mark.parametrize("edit,needle", [
+    (lambda d: d["reactions"][0]["reactants"].__setitem__(1, "X"), "not defined"),
+    (lambda d: d["species"][1].__setitem__("partners", []), "does not list it"),
+    (lambda d: d["species"][0].__setitem__("mw_kda", 50000.0), "molecular weight"),
+    (lambda d: d["species"][1].__setitem__("concentration_M", 1e-12), "less than one molecule"),
+    (lambda d: d["species"][1].__setitem__("concentration_M", 2e-2), "do not fit the volume"),
+    (lambda d: d["reactions"].append({"reactants": ["ES"], "products": ["E", None],
+                                      "probability": 0.999}), "sum to"),
+    (lambda d: d["reactions"].append({"reactants": ["S", "E"], "products": ["S", "E"],
+                                      "radius_nm": 5, "probability": 0.1}), "second contact"),
+    (lambda d: d["species"][0].pop("concentration_M"), "exactly one of concentration_M"),
+    (lambda d: d.__setitem__("colour", "red"), "unknown key"),
+])
+def test_consistency_checks_catch(edit, needle):
+    d = copy.deepcopy(doc())
+    edit(d)
+    probs = mio.check_model(d)
+    assert any(needle in p for p in probs), probs
+    with pytest.raises(mio.ModelError):
+        mio.load_model(d)
+    assert mio.check_model(doc()) == []
+
+
+def test_threshold_crossings():
+    steps = np.arange(0, 1000, 100)
+    counts = np.zeros((len(steps), 1, 2))
+    counts[:, 0, 1] = [0, 10, 20, 40, 80, 160, 320, 640, 900, 950]
+    vol = 1.0
+    c = monitor.concentration(100, vol)
+    th = [monitor.Threshold(1, above_M=float(c), from_s=0.0, to_s=4e-4, volume_um3=vol),
+          monitor.Threshold(1, above_M=float(c), from_s=0.0, to_s=1.0, volume_um3=vol),
+          monitor.Threshold(1, below_M=float(monitor.concentration(5, vol)), from_s=1e-4,
+                            volume_um3=vol)]
+    hits = monitor.check(steps, counts, 1e-6, th)
+    assert len(hits) == 1 and hits[0].step == 500 and hits[0].threshold is th[1]
