@@ -239,6 +239,8 @@ def main() -> int:
                     help="replay each step as a captured HIP graph (default: direct launches)")
     ap.add_argument("--cell-um", type=float, default=0.0,
                     help="spatial-hash cell size (0: the library's choice)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time candidate cell sizes first and run with the fastest")
     ap.add_argument("--workload", choices=("c2", "c4", "c5"), default="c2",
                     help="c2: the 2M-agent step (agent-updates/s); c4: the batched "
                          "dose x replicate sweep (sims/s vs serial); c5: the serving loop "
@@ -280,6 +282,12 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = None
+    if args.tune:
+        from paper_2606_14603_amd import tune
+        tr = tune.tune_cell(model)
+        args.cell_um = tr.cell_um
+        tuned = {f"{h:.5f}": round(ms, 4) for h, ms in tr.ms_per_step.items()}
     sim = mabm.Sim(model, graphs=args.graph, cell_um=args.cell_um)
     G, h = sim.grid()
     stream = sim.stream
@@ -347,7 +355,7 @@ def main() -> int:
         "config": {"workload": f"c2_mapk: {model.n_agents} agents, 8 species, 12 rules, "
                                f"reflecting sphere R={model.outer_radius_um:.3f} um, dt=1 us",
                    "agents": model.n_agents, "grid": G, "cell_um": round(h, 5),
-                   "graphs": args.graph, "final_step": t,
+                   "graphs": args.graph, "final_step": t, "tuned_ms_per_step": tuned,
                    "live_agents_end": int(counts.sum())},
         "roofline": roof, "kernels": kernels,
         "ms_per_step_kernel_timed": None if ms_direct is None else ms_direct / args.steps,

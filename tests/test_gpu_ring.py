@@ -85,3 +85,12 @@ def test_model_file_runs_like_the_oracle():
                          {"reactants": ["pS"], "products": ["S"], "kcat_per_s": 500.0}]}
     m = model_io.load_model(doc)
     run_pair(m, [1, 10, 30])
+
+
+def test_tuner_picks_a_candidate_and_caches_it(tmp_path):
+    from paper_2606_14603_amd import tune
+    m = W.c2(60_000, seed=3)
+    r = tune.tune_cell(m, steps=5, warm=2, cache_path=str(tmp_path / "cells.json"))
+    assert r.cell_um in r.ms_per_step and len(r.ms_per_step) == len(tune.candidates(m))
+    assert tune.tune_cell(W.c2(60_000, seed=4)).cached
+    say(f"[tune] {m.name}: {r.cell_um:.4f} um from {r.ms_per_step}")

@@ -112,3 +112,18 @@ def test_threshold_crossings():
                             volume_um3=vol)]
     hits = monitor.check(steps, counts, 1e-6, th)
     assert len(hits) == 1 and hits[0].step == 500 and hits[0].threshold is th[1]
+
+
+def test_tuner_candidates_respect_the_contact_radius():
+    import workloads as W
+    from paper_2606_14603_amd import tune
+    m = W.c2(2_000_000)
+    c = tune.candidates(m)
+    ext = 10.0
+    grids = sorted(int(ext / h) for h in c)
+    assert 128 in grids and 64 in grids and 256 in grids  # around one cell per agent
+    assert all(h >= 1.01 * 0.010 for h in c)
+    # the finest 8-cell-stencil grid: h >= 2.02 x 10 nm
+    assert int(ext / (2.02 * 0.010)) in grids or 512 in grids
+    assert tune.shape_key(m) == tune.shape_key(W.c2(2_000_000, seed=5))
+    assert tune.shape_key(m) != tune.shape_key(W.c2(200_000))
