@@ -48,8 +48,9 @@ KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (53, 0, 0),
 # threshold, four uniforms, two logarithms, two square roots, two sin/cos
 # evaluations, the displacement, the sphere test, the cell coordinates and
 # their Morton interleave), counted as 32-bit operations (a 32x32->64 product
-# = 2, a correctly rounded divide or square root = 1), is 339 per agent.
-MOVE_OPS_PER_AGENT = 339
+# = 2, a fused multiply-add = 2, a correctly rounded divide or square root =
+# 1), is 323 per agent.
+MOVE_OPS_PER_AGENT = 323
 # One 32-bit lane operation per clock per lane: 256 CUs x 64 lanes x 2.4 GHz
 # (the 157.3 TFLOP/s fp32 figure counts an FMA as 2 and packed pairs as 2).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12

@@ -158,10 +158,10 @@ static float unif_plus(uint32_t w) { return (float)((w >> 8) + 1u) * 0x1p-24f; }
 /* ------------------------------------------------------------------------
  * O3 helper: natural logarithm for x in (0, 1].  x = m * 2^e with m folded
  * into (sqrt(1/2), sqrt(2)]; log m = 2 atanh(s), s = (m-1)/(m+1), summed as
- * the Maclaurin series of atanh up to s^11 (|s| < 0.172, so the first
- * omitted term is below 1e-10 relative).  ln 2 is split into a 16-bit head,
- * exact when multiplied by the small exponent, plus the float nearest the
- * remainder.
+ * the Maclaurin series of atanh up to s^9 (|s| < 0.172, so the first
+ * omitted term, s^11/11, is below 4e-10 relative) by Horner's rule with
+ * fused multiply-adds.  ln 2 is split into a 16-bit head, exact when
+ * multiplied by the small exponent, plus the float nearest the remainder.
  * ---------------------------------------------------------------------- */
 float orc_log(float x)
 {
@@ -180,23 +180,23 @@ float orc_log(float x)
     }
     float s = (m - 1.0f) / (m + 1.0f);
     float s2 = s * s;
-    float q = 1.0f / 11.0f;
-    q = q * s2 + 1.0f / 9.0f;
-    q = q * s2 + 1.0f / 7.0f;
-    q = q * s2 + 1.0f / 5.0f;
-    q = q * s2 + 1.0f / 3.0f;
+    float q = 1.0f / 9.0f;
+    q = fmaf(q, s2, 1.0f / 7.0f);
+    q = fmaf(q, s2, 1.0f / 5.0f);
+    q = fmaf(q, s2, 1.0f / 3.0f);
     q = q * s2;
-    float lm = (s + s * q) * 2.0f;
+    float lm = fmaf(s, q, s) * 2.0f;
     float fe = (float)e;
-    return fe * LN2_HEAD + (fe * LN2_TAIL + lm);
+    return fmaf(fe, LN2_HEAD, fmaf(fe, LN2_TAIL, lm));
 }
 
 /* ------------------------------------------------------------------------
  * O3 helper: sin and cos of 2*pi*a for a in [0, 1) on the 2^-24 grid.
  * Quadrant q = floor(4a) and remainder r = 4a - q are exact; r > 1/2 is
  * folded to 1 - r (exact) with sin and cos swapped; x = r * (pi/2) lies in
- * [0, pi/4], where the Maclaurin series of sin (to x^11) and cos (to x^12)
- * are summed by Horner's rule with coefficients +-1/n!.
+ * [0, pi/4], where the Maclaurin series of sin (to x^9) and cos (to x^8)
+ * are summed by Horner's rule with fused multiply-adds and coefficients
+ * +-1/n! (first omitted terms below 2e-9 and 5e-8 at pi/4).
  * ---------------------------------------------------------------------- */
 void orc_sincos2pi(float a, float* out_s, float* out_c)
 {
@@ -208,21 +208,17 @@ void orc_sincos2pi(float a, float* out_s, float* out_c)
     if (fold) r = 1.0f - r;
     float x = r * PI_2;
     float x2 = x * x;
-    float ps = -(1.0f / 39916800.0f);
-    ps = ps * x2 + 1.0f / 362880.0f;
-    ps = ps * x2 + -(1.0f / 5040.0f);
-    ps = ps * x2 + 1.0f / 120.0f;
-    ps = ps * x2 + -(1.0f / 6.0f);
+    float ps = 1.0f / 362880.0f;
+    ps = fmaf(ps, x2, -(1.0f / 5040.0f));
+    ps = fmaf(ps, x2, 1.0f / 120.0f);
+    ps = fmaf(ps, x2, -(1.0f / 6.0f));
     ps = ps * x2;
-    float sx = x + x * ps;
-    float pc = 1.0f / 479001600.0f;
-    pc = pc * x2 + -(1.0f / 3628800.0f);
-    pc = pc * x2 + 1.0f / 40320.0f;
-    pc = pc * x2 + -(1.0f / 720.0f);
-    pc = pc * x2 + 1.0f / 24.0f;
-    pc = pc * x2 + -0.5f;
-    pc = pc * x2;
-    float cx = 1.0f + pc;
+    float sx = fmaf(x, ps, x);
+    float pc = 1.0f / 40320.0f;
+    pc = fmaf(pc, x2, -(1.0f / 720.0f));
+    pc = fmaf(pc, x2, 1.0f / 24.0f);
+    pc = fmaf(pc, x2, -0.5f);
+    float cx = fmaf(pc, x2, 1.0f);
     float s1 = fold ? cx : sx;
     float c1 = fold ? sx : cx;
     switch (q & 3) {
@@ -694,7 +690,7 @@ static void phase_move(orc_sim* s, uint32_t i)
     float g[3];
     gauss3_w(w, g);
     float sg = s->sigma[sp];
-    float x1 = x + sg * g[0], y1 = y + sg * g[1], z1 = z + sg * g[2];
+    float x1 = fmaf(sg, g[0], x), y1 = fmaf(sg, g[1], y), z1 = fmaf(sg, g[2], z);
 
     /* O4: boundaries */
     if (s->geometry == ORC_PERIODIC_BOX) {

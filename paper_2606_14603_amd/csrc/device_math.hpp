@@ -2,9 +2,10 @@
 // the geometry predicates of the molecule-agent step, for gfx950.
 //
 // Everything here is a pure function of its arguments and uses only IEEE
-// binary32 +, -, *, / and sqrt (the library is built with -ffp-contract=off,
-// denormals kept, correctly rounded division and square root), so every
-// result is reproducible bit for bit from the step definition.
+// binary32 +, -, *, /, sqrt and explicit fused multiply-add (the library is
+// built with -ffp-contract=off, so no other operation is fused; denormals
+// are kept, division and square root correctly rounded), so every result is
+// reproducible bit for bit from the step definition.
 #pragma once
 
 #include "engine.hpp"
@@ -54,8 +55,8 @@ __device__ __forceinline__ float u01_open0(uint32_t w) { return float((w >> 8) +
 
 // ln x for x in (0, 1]: split x = m 2^e, fold m above sqrt 2 down by one
 // octave, then ln m = 2 atanh(s) with s = (m-1)/(m+1) and the odd series of
-// atanh through s^11 by Horner's rule; e ln 2 is added as a 16-bit head
-// (exact product) and a float tail.
+// atanh through s^9 by Horner's rule with fused multiply-adds; e ln 2 is
+// added as a 16-bit head (exact product) and a float tail.
 __device__ __forceinline__ float ln_unit(float x)
 {
     const uint32_t b = __float_as_uint(x);
@@ -67,20 +68,20 @@ __device__ __forceinline__ float ln_unit(float x)
     }
     const float s = (m - 1.0f) / (m + 1.0f);
     const float s2 = s * s;
-    float h = 1.0f / 11.0f;
-    h = h * s2 + 1.0f / 9.0f;
-    h = h * s2 + 1.0f / 7.0f;
-    h = h * s2 + 1.0f / 5.0f;
-    h = h * s2 + 1.0f / 3.0f;
+    float h = 1.0f / 9.0f;
+    h = __builtin_fmaf(h, s2, 1.0f / 7.0f);
+    h = __builtin_fmaf(h, s2, 1.0f / 5.0f);
+    h = __builtin_fmaf(h, s2, 1.0f / 3.0f);
     h = h * s2;
-    const float ln_m = (s + s * h) * 2.0f;
+    const float ln_m = __builtin_fmaf(s, h, s) * 2.0f;
     const float fe = float(e);
-    return fe * 0x1.62e4p-1f + (fe * 0x1.7f7d1cp-20f + ln_m);
+    return __builtin_fmaf(fe, 0x1.62e4p-1f, __builtin_fmaf(fe, 0x1.7f7d1cp-20f, ln_m));
 }
 
 // sin and cos of 2 pi a, a in [0,1) on the 2^-24 grid: exact quadrant and
 // remainder, fold of the remainder above 1/2 (swapping sin and cos), and the
-// Maclaurin series of sin (x^11) and cos (x^12) on [0, pi/4].
+// Maclaurin series of sin (x^9) and cos (x^8) on [0, pi/4] by Horner's rule
+// with fused multiply-adds.
 __device__ __forceinline__ void sincos_turn(float a, float& sn, float& cs)
 {
     const float a4 = a * 4.0f;
@@ -90,21 +91,17 @@ __device__ __forceinline__ void sincos_turn(float a, float& sn, float& cs)
     if (fold) r = 1.0f - r;
     const float x = r * 0x1.921fb6p+0f;  // pi/2 rounded to float
     const float x2 = x * x;
-    float ps = -(1.0f / 39916800.0f);
-    ps = ps * x2 + 1.0f / 362880.0f;
-    ps = ps * x2 + -(1.0f / 5040.0f);
-    ps = ps * x2 + 1.0f / 120.0f;
-    ps = ps * x2 + -(1.0f / 6.0f);
+    float ps = 1.0f / 362880.0f;
+    ps = __builtin_fmaf(ps, x2, -(1.0f / 5040.0f));
+    ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);
+    ps = __builtin_fmaf(ps, x2, -(1.0f / 6.0f));
     ps = ps * x2;
-    const float sx = x + x * ps;
-    float pc = 1.0f / 479001600.0f;
-    pc = pc * x2 + -(1.0f / 3628800.0f);
-    pc = pc * x2 + 1.0f / 40320.0f;
-    pc = pc * x2 + -(1.0f / 720.0f);
-    pc = pc * x2 + 1.0f / 24.0f;
-    pc = pc * x2 + -0.5f;
-    pc = pc * x2;
-    const float cx = 1.0f + pc;
+    const float sx = __builtin_fmaf(x, ps, x);
+    float pc = 1.0f / 40320.0f;
+    pc = __builtin_fmaf(pc, x2, -(1.0f / 720.0f));
+    pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
+    pc = __builtin_fmaf(pc, x2, -0.5f);
+    const float cx = __builtin_fmaf(pc, x2, 1.0f);
     const float s1 = fold ? cx : sx;
     const float c1 = fold ? sx : cx;
     switch (quad & 3) {

@@ -243,7 +243,7 @@ __device__ __forceinline__ void move_agent(const Dev& d, const Tables& T, const 
     float z0, z1, z2;
     normals3(w, z0, z1, z2);
     const float sg = T.sigma[s];
-    float x1 = x + sg * z0, y1 = y + sg * z1, w1 = z + sg * z2;
+    float x1 = __builtin_fmaf(sg, z0, x), y1 = __builtin_fmaf(sg, z1, y), w1 = __builtin_fmaf(sg, z2, z);
     if (T.geometry == kBox) {
         x1 = wrap_box(T, x1);
         y1 = wrap_box(T, y1);
