@@ -32,6 +32,8 @@
 // here is a dense contraction.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "device_math.hpp"
 #include "engine.hpp"
 
@@ -604,26 +606,30 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
-// kPChunk = 4 x kBlock sorted agents: each thread reads the four claimer
-// flags of its agents as one word, a wave-level prefix places them, and one
-// LDS atomic per wave reserves the list space.  Returns the list length.
-// `word` is the thread's flag word, loaded by the caller before anything
-// else so that its latency overlaps the kernel's other set-up loads; the
-// caller has zeroed *count before a barrier.
+// kPChunk = kClaimPer x kBlock sorted agents: each thread reads the claimer
+// flags of its kClaimPer agents as one word, a wave-level prefix places
+// them, and one LDS atomic per wave reserves the list space.  `word` is
+// loaded by the caller before anything else so that its latency overlaps
+// the kernel's other set-up loads; the caller has zeroed *count before a
+// barrier.  Returns the list length.
+constexpr int kClaimPer = kPChunk / kBlock;
+static_assert(kClaimPer == 2 || kClaimPer == 4, "two or four claimer flags per thread");
+using FlagWord = std::conditional_t<kClaimPer == 4, uint32_t, uint16_t>;
+
 __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t first, uint32_t last,
                                                      uint32_t* list, uint32_t* count)
 {
-    static_assert(kPChunk == 4 * kBlock, "four agents per thread");
-    const uint32_t k0 = first + 4u * threadIdx.x;
+    const uint32_t k0 = first + uint32_t(kClaimPer) * threadIdx.x;
     uint32_t flags = 0;
     if (k0 < last) {
         // flags past `last` are dropped
         flags = word;
-        const uint32_t valid = last - k0 >= 4u ? 4u : last - k0;
-        if (valid < 4u) flags &= (1u << (8u * valid)) - 1u;
+        const uint32_t valid = last - k0;
+        if (valid < uint32_t(kClaimPer)) flags &= (1u << (8u * valid)) - 1u;
     }
-    const uint32_t mine = (flags & 0xFFu ? 1u : 0u) + (flags & 0xFF00u ? 1u : 0u) +
-                          (flags & 0xFF0000u ? 1u : 0u) + (flags & 0xFF000000u ? 1u : 0u);
+    uint32_t mine = 0;
+#pragma unroll
+    for (int b = 0; b < kClaimPer; ++b) mine += (flags >> (8 * b)) & 0xFFu ? 1u : 0u;
     uint32_t incl = mine;
     const int lane = lane_id();
 #pragma unroll
@@ -636,8 +642,8 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
     if (lane == 0 && wave_total) base = atomicAdd(count, wave_total);
     base = __shfl(base, 0, 64) + incl - mine;
 #pragma unroll
-    for (uint32_t b = 0; b < 4u; ++b)
-        if ((flags >> (8u * b)) & 0xFFu) list[base++] = k0 + b;
+    for (int b = 0; b < kClaimPer; ++b)
+        if ((flags >> (8 * b)) & 0xFFu) list[base++] = k0 + uint32_t(b);
     __syncthreads();
     return *count;
 }
@@ -804,7 +810,8 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     // padded to whole chunks and the grid covers the capacity, so the word
     // is in bounds even past the live agents (whose count arrives with the
     // control block).
-    const uint32_t word = *reinterpret_cast<const uint32_t*>(d.sclaim + first + 4u * threadIdx.x);
+    const uint32_t word =
+        *reinterpret_cast<const FlagWord*>(d.sclaim + first + uint32_t(kClaimPer) * threadIdx.x);
     const uint32_t n = d.ctl->n_binned;
     const uint32_t t = d.ctl->s[p].t;
     if (first >= n) return;
