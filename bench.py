@@ -55,15 +55,16 @@ MOVE_OPS_PER_AGENT = 323
 # (the 157.3 TFLOP/s fp32 figure counts an FMA as 2 and packed pairs as 2).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# HBM traffic of move per launch from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch, averaged over 55 dispatches of
+# HBM traffic of the step kernels per launch from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch, averaged over 55 dispatches of
 # "bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile
 # --copy-calib-mb 512"), scaled by what the same counters read for the
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
-TRAFFIC = {"kernel": "move", "fetch_kib": 19680.0, "write_kib": 58998.0, "fetch_scale": 2.0,
-           "write_scale": 1.0,
-           "sources_sha256": "0b12ef1a86e2a4448e1d183456985899c61a5601c890fa2572e5fbd9e3d9242f"}
+TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
+           "sources_sha256": "5a85febc8109ac21be77ad6eb628ee32078213f6dd9018821fc63ba67499a499",
+           # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
+           "kib": {"move": (19680.7, 58998.6), "scan": (4623.8, 16416.1), "scatter": (33152.7, 46323.9), "propose": (19271.7, 2952.1), "finish": (15.9, 0.4)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
@@ -78,11 +79,13 @@ def kernel_sources_sha() -> str:
 
 
 def measured_traffic(kernel: str):
-    """Calibrated HBM bytes per launch, or None if the counters are stale."""
+    """Calibrated HBM bytes per launch of the c2 step kernel, or None if
+    there are no counters for it or they were taken on other sources."""
     t = TRAFFIC
-    if t["kernel"] != kernel or t["fetch_kib"] is None or t["sources_sha256"] != kernel_sources_sha():
+    if kernel not in t["kib"] or t["sources_sha256"] != kernel_sources_sha():
         return None
-    return int(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+    f, w = t["kib"][kernel]
+    return int(1024 * (f * t["fetch_scale"] + w * t["write_scale"]))
 
 
 def copy_ceiling_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
@@ -101,6 +104,13 @@ def copy_ceiling_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
+def describe(model) -> str:
+    geo = {0: f"periodic box {model.box_um:g} um", 1: f"reflecting sphere R={model.outer_radius_um:.3f} um",
+           2: f"nested spheres R_in={model.inner_radius_um:.3f} um, R_out={model.outer_radius_um:.3f} um"}
+    return (f"{model.name}: {model.n_agents} agents, {len(model.species)} species, "
+            f"{len(model.rules)} rules, {geo[model.geometry]}, dt={model.dt_s * 1e6:g} us")
 
 
 def cpu_baseline(model, budget_s: float = 12.0, max_steps: int = 40) -> dict:
@@ -242,10 +252,12 @@ def main() -> int:
                     help="spatial-hash cell size (0: the library's choice)")
     ap.add_argument("--tune", action="store_true",
                     help="time candidate cell sizes first and run with the fastest")
-    ap.add_argument("--workload", choices=("c2", "c4", "c5"), default="c2",
-                    help="c2: the 2M-agent step (agent-updates/s); c4: the batched "
-                         "dose x replicate sweep (sims/s vs serial); c5: the serving loop "
-                         "(p50/p99 latency, sims/s vs FIFO)")
+    ap.add_argument("--workload", choices=("c1", "c2", "c3", "c4", "c5"), default="c2",
+                    help="c2: the 2M-agent cascade step (agent-updates/s, the headline); "
+                         "c1: A+B<->C, 20k agents in a periodic box; c3: nested "
+                         "compartments, 5M agents, births; c4: the batched dose x replicate "
+                         "sweep (sims/s vs serial); c5: the serving loop (p50/p99 latency, "
+                         "sims/s vs FIFO)")
     ap.add_argument("--serve-requests", type=int, default=256, help="c5: requests")
     ap.add_argument("--serve-chunk", type=int, default=256, help="c5: steps per turn")
     ap.add_argument("--serve-active", type=int, default=64, help="c5: simulations admitted at once")
@@ -275,7 +287,12 @@ def main() -> int:
     if args.workload == "c5":
         print(json.dumps(run_serving(args, torch, mabm, W)), flush=True)
         return 0
-    model = W.c2(args.agents)
+    if args.workload == "c1":
+        model = W.c1()
+    elif args.workload == "c3":
+        model = W.c3(args.agents if args.agents != 2_000_000 else 5_000_000)
+    else:
+        model = W.c2(args.agents)
     if args.copy_calib_mb:
         src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -311,7 +328,8 @@ def main() -> int:
     value = updates / (ms / 1e3)
     live = updates / args.steps
     counts, t = sim.counts()
-    claimers = int(counts[[0, 3, 6]].sum())  # kinase1, p-kinase2, phosphatase claim
+    claim_sp = sorted({r.reactants[0] for r in model.rules if r.kind == W.BIMOL})
+    claimers = int(counts[claim_sp].sum())
 
     # the same number of steps again, each kernel's dispatch stamping HIP
     # events at its start and end (direct launches), for per-kernel durations
@@ -328,6 +346,11 @@ def main() -> int:
                 us = 1e3 * tot / launches
                 kernels[name] = {"launches": launches, "avg_us": round(us, 3),
                                  "alg_bytes": int(alg), "alg_gbs": round(alg / us / 1e3, 1)}
+                tb = measured_traffic(name) if args.workload == "c2" and live > 1.9e6 else None
+                if tb is not None:
+                    kernels[name]["traffic_bytes"] = tb
+                    kernels[name]["traffic_gbs"] = round(tb / us / 1e3, 1)
+                    kernels[name]["traffic_hbm_frac"] = round(tb / us / 1e3 / HBM_PEAK_GBS, 4)
         dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
         us = kernels[dom]["avg_us"]
         if dom == "move":
@@ -341,7 +364,7 @@ def main() -> int:
             achieved = kernels[dom]["alg_gbs"]
             roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-        roof["traffic"] = measured_traffic(dom)
+        roof["traffic"] = kernels[dom].get("traffic_bytes")
         roof["alg_bytes_per_launch"] = kernels[dom]["alg_bytes"]
         roof["hbm_frac_alg_bytes"] = round(kernels[dom]["alg_gbs"] / HBM_PEAK_GBS, 4)
         step_bytes = sum(k["alg_bytes"] for k in kernels.values())
@@ -353,8 +376,7 @@ def main() -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"c2_mapk: {model.n_agents} agents, 8 species, 12 rules, "
-                               f"reflecting sphere R={model.outer_radius_um:.3f} um, dt=1 us",
+        "config": {"workload": describe(model),
                    "agents": model.n_agents, "grid": G, "cell_um": round(h, 5),
                    "graphs": args.graph, "final_step": t, "tuned_ms_per_step": tuned,
                    "live_agents_end": int(counts.sum())},

@@ -606,12 +606,13 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
-// kPChunk = kClaimPer x kBlock sorted agents: each thread reads the claimer
-// flags of its kClaimPer agents as one word, a wave-level prefix places
-// them, and one LDS atomic per wave reserves the list space.  `word` is
-// loaded by the caller before anything else so that its latency overlaps
-// the kernel's other set-up loads; the caller has zeroed *count before a
-// barrier.  Returns the list length.
+// kPChunk = kClaimPer x kBlock sorted agents, in agent order: each thread
+// reads the claimer flags of its kClaimPer agents as one word, a wave-level
+// prefix places them within the wave, and the waves' totals, exchanged
+// through LDS, place the waves.  The order is the same in every workgroup
+// that compacts the chunk, which lets several share its claimers.  `word`
+// is loaded by the caller before anything else so that its latency
+// overlaps the kernel's other set-up loads.  Returns the list length.
 constexpr int kClaimPer = kPChunk / kBlock;
 static_assert(kClaimPer == 2 || kClaimPer == 4, "two or four claimer flags per thread");
 using FlagWord = std::conditional_t<kClaimPer == 4, uint32_t, uint16_t>;
@@ -637,15 +638,22 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
         const uint32_t u = __shfl_up(incl, o, 64);
         if (lane >= o) incl += u;
     }
-    const uint32_t wave_total = __shfl(incl, 63, 64);
-    uint32_t base = 0;
-    if (lane == 0 && wave_total) base = atomicAdd(count, wave_total);
-    base = __shfl(base, 0, 64) + incl - mine;
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int wv = int(threadIdx.x) >> 6;
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t base = incl - mine, total = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) {
+        if (k < wv) base += wsum[k];
+        total += wsum[k];
+    }
 #pragma unroll
     for (int b = 0; b < kClaimPer; ++b)
         if ((flags >> (8 * b)) & 0xFFu) list[base++] = k0 + uint32_t(b);
+    if (threadIdx.x == 0) *count = total;
     __syncthreads();
-    return *count;
+    return total;
 }
 
 // ---------------------------------------------------------------------------
@@ -798,14 +806,19 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
+__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t plocal[kPChunk];
     __shared__ PairLds P;
     __shared__ uint32_t count, nprop, pbase;
     const Tables& T = *d.tab;
-    const uint32_t first = xcd_chunk() * kPChunk;
+    // `split` workgroups share a chunk (small simulations, whose few chunks
+    // would otherwise leave the claimers to a few workgroups): each compacts
+    // the chunk and searches every split-th pass of its claimers
+    const uint32_t g = xcd_chunk();
+    const uint32_t share = g % split;
+    const uint32_t first = g / split * kPChunk;
     // The thread's four claimer flags, requested first.  The flag array is
     // padded to whole chunks and the grid covers the capacity, so the word
     // is in bounds even past the live agents (whose count arrives with the
@@ -837,7 +850,7 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p)
     const int ncell = T.stencil8 ? 8 : 27;
     const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
     const int nsub = kBlock / width;
-    for (uint32_t q = uint32_t(sub); q < nl; q += uint32_t(nsub)) {
+    for (uint32_t q = uint32_t(sub) + share * uint32_t(nsub); q < nl; q += uint32_t(nsub) * split) {
         const uint32_t j = list[q];
         const uint4 rj = A.rec[j];
         if (B)
@@ -969,6 +982,7 @@ __global__ void k_zero_counts(Dev d, int cur, unsigned long long* tslot)
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
 static constexpr unsigned kFinishBlocks = 64;
+static constexpr unsigned kPropMinBlocks = 2048;
 static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
@@ -1005,8 +1019,12 @@ void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvent
 }
 void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
-    if (d.n_sims > 1) go(k_propose<true>, chunks_for(d.capacity), kBlock, s, ev, d, p);
-    else go(k_propose<false>, chunks_for(d.capacity), kBlock, s, ev, d, p);
+    // enough workgroups to fill the chip: chunks shared by up to 16
+    const unsigned chunks = chunks_for(d.capacity);
+    unsigned split = 1;
+    while (split < 16 && chunks * split * 2 <= kPropMinBlocks) split *= 2;
+    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split);
+    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split);
 }
 void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
