@@ -27,6 +27,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "agent-updates/s at 2M agents; batched sweep sims/s vs serial; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# The paper publishes whole-run wall-clock times only (Sec. 3.2): about 10 h
+# and 1.5 h for 8 h of simulated time at 3 pL and 0.3 pL, on an NVIDIA L4
+# and one NVIDIA A100; no per-step rate and no time step.  Context only.
+PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time took ~10 h (3 pL, "
+                 "~4.6M agents) and ~1.5 h (0.3 pL, ~0.46M agents) on NVIDIA L4 / A100, "
+                 "i.e. ~2.4e6-3.6e6 agent x simulated-s per wall-s; its time step is not stated")
 
 # Algorithmic bytes per launch of each step kernel: bytes per live agent (a),
 # per claimer (q) and per cell of the spatial hash (c) that the kernel must
@@ -62,9 +68,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
 TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "5a85febc8109ac21be77ad6eb628ee32078213f6dd9018821fc63ba67499a499",
+           "sources_sha256": "730fbc079670a9f03ddd5152eb9a9f29c1659aafbd4156070771dd3cf508b6ee",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19680.7, 58998.6), "scan": (4623.8, 16416.1), "scatter": (33152.7, 46323.9), "propose": (19271.7, 2952.1), "finish": (15.9, 0.4)}}
+           "kib": {"move": (19679.9, 58998.8), "scan": (4623.8, 16416.1), "scatter": (33143.2, 46321.7), "propose": (19269.8, 2951.9), "finish": (17.7, 0.4)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
@@ -145,7 +151,8 @@ def run_sweep(args, torch, mabm, W) -> dict:
     warm.step(3)
     warm.counts()
     del warm
-    batch = mabm.Batch(models)
+    # each step of the batch is replayed from a captured graph
+    batch = mabm.Batch(models, graphs=True)
     batch.grid()  # finalize: tables, placement
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -160,7 +167,7 @@ def run_sweep(args, torch, mabm, W) -> dict:
     sample = list(range(0, n, max(1, n // args.sweep_sample)))[:args.sweep_sample]
     ms_serial, same = 0.0, True
     for k in sample:
-        sim = mabm.Sim(models[k])
+        sim = mabm.Sim(models[k], graphs=True)
         sim.grid()
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -370,6 +377,9 @@ def main() -> int:
         step_bytes = sum(k["alg_bytes"] for k in kernels.values())
         roof["step_alg_bytes_per_update"] = round(step_bytes / live, 1)
         roof["step_alg_gbs"] = round(step_bytes * args.steps / (ms * 1e-3) / 1e9, 1)
+        # the whole step against the HBM roofline of its algorithmic bytes
+        roof["step_hbm_roofline_updates_per_s"] = round(HBM_PEAK_GBS * 1e9 / (step_bytes / live), -6)
+        roof["step_hbm_frac"] = round(value / roof["step_hbm_roofline_updates_per_s"], 4)
         roof["copy_ceiling_gbs"] = round(copy_ceiling_gbs(torch), 1)
     out = {
         "metric": METRIC, "value": value, "unit": "agent-updates/s", "n_gpus": 1,
@@ -383,6 +393,7 @@ def main() -> int:
         "roofline": roof, "kernels": kernels,
         "ms_per_step_kernel_timed": None if ms_direct is None else ms_direct / args.steps,
     }
+    out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(model)
     print(json.dumps(out), flush=True)
