@@ -297,6 +297,7 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
         if (u.kind == MABM_BIMOL) {
             T.rule_of[u.reactant[0]][u.reactant[1]] = (int8_t)r;
             T.claimer[u.reactant[0]] = 1;
+            T.claim_r2max[u.reactant[0]] = std::max(T.claim_r2max[u.reactant[0]], R.r2);
             rmax = std::max(rmax, (double)u.radius_um);
             s->has_bimol = true;
         }

@@ -78,6 +78,7 @@ struct Tables {
     int32_t init_comp[kMaxSpecies];
     float sigma[kMaxSpecies];
     uint8_t claimer[kMaxSpecies];
+    float claim_r2max[kMaxSpecies];  // largest squared contact radius of a claimer's rules
     uint8_t uni_n[kMaxSpecies][2];
     uint8_t uni_rule[kMaxSpecies][2][kMaxUni];
     uint64_t uni_thr[kMaxSpecies][2][kMaxUni];

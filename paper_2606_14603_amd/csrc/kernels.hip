@@ -676,17 +676,15 @@ struct Best {
 struct PairLds {
     int8_t rule_of[kMaxSpecies * kMaxSpecies];
     float r2[kMaxRules];
+    float r2max[kMaxSpecies];  // per claimer species, its largest r2
 };
 
 __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, const Agents& A,
                                          const uint4& rk, uint32_t k, uint32_t self, uint32_t s,
-                                         float x, float y, float z, int comp, Best& b)
+                                         float x, float y, float z, int comp, float r2max,
+                                         Best& b)
 {
-    const uint32_t sb = rk.w & 0xFFu;
-    const int r = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : -1;
-    if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
     const float bx = __uint_as_float(rk.x), by = __uint_as_float(rk.y), bz = __uint_as_float(rk.z);
-    if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
     float dx = bx - x, dy = by - y, dz = bz - z;
     if (T.geometry == kBox) {
         if (dx > T.halfL) dx -= T.L; else if (dx < -T.halfL) dx += T.L;
@@ -694,6 +692,13 @@ __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, cons
         if (dz > T.halfL) dz -= T.L; else if (dz < -T.halfL) dz += T.L;
     }
     const float d2 = dx * dx + dy * dy + dz * dz;
+    // no rule of the claimer's species reaches beyond r2max, so nearly
+    // every candidate stops here, before the rule lookup
+    if (!(d2 <= r2max)) return;
+    const uint32_t sb = rk.w & 0xFFu;
+    const int r = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : -1;
+    if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
+    if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
     if (!(d2 <= P.r2[r])) return;
     if (b.idx != kNone && d2 > b.d2) return;
     const uint32_t bid = A.id[k];
@@ -732,6 +737,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
     const uint32_t s = rj.w & 0xFFu;
+    const float r2max = P.r2max[s];
     const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
     const int comp = compartment(T, x, y, z);
     const float pp[3] = {x, y, z};
@@ -778,10 +784,10 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         if (a1) r1 = A.rec[k0 + 1];
         if (b0) r2 = A.rec[k1];
         if (b1) r3 = A.rec[k1 + 1];
-        if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, b);
-        if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, b);
-        if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, b);
-        if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, b);
+        if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, r2max, b);
+        if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, r2max, b);
+        if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, r2max, b);
+        if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, r2max, b);
         k0 += 2;
         k1 += 2;
     }
@@ -835,6 +841,7 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
         uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
         for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
         for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kBlock) P.r2max[q] = T.claim_r2max[q];
         if (threadIdx.x == 0) {
             nprop = 0;
             count = 0;
