@@ -209,18 +209,25 @@ def run_serving(args, torch, mabm, W) -> dict:
     every admitted simulation resident and advances them on streams of their
     own.  Admission: arrival order, while the summed arenas fit the budget."""
     from paper_2606_14603_amd import serve
-    models = W.c5_requests(args.serve_requests, seed=0)
+
+    def progress(r):  # one line per completed request, on stderr
+        print(f"[serve] {r.name} done at {r.completed_s:.2f} s ({r.agents} agents, {r.steps} steps)",
+              file=sys.stderr, flush=True)
+
+    models = W.c5_requests(args.serve_requests, seed=0, n_max=args.serve_max_agents,
+                           h_min=args.serve_min_steps, h_max=args.serve_max_steps)
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.85 * free) if args.serve_budget_gb <= 0 else int(args.serve_budget_gb * 2**30)
     # load the code objects and the graph path once
     serve.Server(budget, max_active=2).run(W.c5_requests(2, seed=99, n_max=60_000, h_max=300),
                                            [0.0, 0.0])
-    fifo = serve.Server(budget, max_active=1, chunk=args.serve_chunk)
+    fifo = serve.Server(budget, max_active=1, chunk=args.serve_chunk, progress=progress)
     cap = serve.summarize(fifo.run(models, np.zeros(len(models))))
     rate = 0.7 * cap["sims_per_s"]
     arrivals = W.poisson_arrivals(len(models), rate, seed=0)
     res_fifo = fifo.run(models, arrivals)
-    conc = serve.Server(budget, max_active=args.serve_active, chunk=args.serve_chunk)
+    conc = serve.Server(budget, max_active=args.serve_active, chunk=args.serve_chunk,
+                        progress=progress, fill_agents=args.serve_fill_agents)
     cap_conc = serve.summarize(conc.run(models, np.zeros(len(models))))
     res_conc = conc.run(models, arrivals)
     s_fifo, s_conc = serve.summarize(res_fifo), serve.summarize(res_conc)
@@ -232,10 +239,12 @@ def run_serving(args, torch, mabm, W) -> dict:
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c5_requests: {len(models)} requests, random closed subsets of "
-                               f"the cascade's rules, 50k-1M agents, 200-2000 steps, Poisson "
+                               f"the cascade's rules, 50k-{args.serve_max_agents // 1000}k agents, "
+                               f"{args.serve_min_steps}-{args.serve_max_steps} steps, Poisson "
                                f"arrivals at 0.7 x the FIFO capacity",
                    "arrival_rate_per_s": rate, "budget_bytes": budget,
-                   "chunk_steps": args.serve_chunk, "max_active": args.serve_active},
+                   "chunk_steps": args.serve_chunk, "max_active": args.serve_active,
+                   "fill_agents": args.serve_fill_agents},
         "p50_s": s_conc["p50_s"], "p99_s": s_conc["p99_s"],
         "concurrent": s_conc, "fifo": s_fifo, "fifo_capacity": cap,
         "concurrent_capacity": cap_conc,
@@ -267,6 +276,13 @@ def main() -> int:
                          "sims/s vs FIFO)")
     ap.add_argument("--serve-requests", type=int, default=256, help="c5: requests")
     ap.add_argument("--serve-chunk", type=int, default=256, help="c5: steps per turn")
+    ap.add_argument("--serve-fill-agents", type=int, default=4_000_000,
+                    help="c5: the concurrent server admits no more while its simulations "
+                         "hold this many agents")
+    ap.add_argument("--serve-max-agents", type=int, default=1_000_000,
+                    help="c5: largest request (log-uniform from 50k)")
+    ap.add_argument("--serve-min-steps", type=int, default=200, help="c5: shortest horizon")
+    ap.add_argument("--serve-max-steps", type=int, default=2000, help="c5: longest horizon")
     ap.add_argument("--serve-active", type=int, default=64, help="c5: simulations admitted at once")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="c5: HBM budget for admitted arenas (0: 85%% of free memory)")

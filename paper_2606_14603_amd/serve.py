@@ -49,16 +49,21 @@ class _Active:
 class Server:
     """``budget_bytes``: HBM the admitted arenas may hold together;
     ``chunk``: steps enqueued per simulation per turn; ``max_active``:
-    simulations admitted at once (1 = FIFO, one request at a time)."""
+    simulations admitted at once (1 = FIFO, one request at a time);
+    ``fill_agents``: admission stops while the admitted simulations hold at
+    least this many agents, enough to fill the GPU (a large request then
+    runs nearly alone, as under FIFO, while small ones overlap)."""
 
     def __init__(self, budget_bytes: int, chunk: int = 256, max_active: int = 64,
-                 device: str = "cuda"):
+                 device: str = "cuda", progress=None, fill_agents: int = 1 << 62):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
         self.max_active = int(max_active)
         self.device = device
+        self.progress = progress  # called with each Result as it completes
+        self.fill_agents = int(fill_agents)
         self._streams: List = []
 
     def _stream(self):
@@ -86,7 +91,8 @@ class Server:
             while queue and len(active) < self.max_active:
                 arr, m = queue[0]
                 need = arena_bytes(m)
-                if used + need > self.budget and active:
+                if active and (used + need > self.budget or
+                               sum(x.model.n_agents for x in active) >= self.fill_agents):
                     break
                 queue.popleft()
                 a = _Active()
@@ -105,6 +111,8 @@ class Server:
                     done.append(Result(a.model.name, a.arrival, a.admitted,
                                        time.perf_counter() - t0, int(a.model.steps),
                                        int(a.model.n_agents), counts))
+                    if self.progress:
+                        self.progress(done[-1])
                     self._streams.append(a.sim.stream)
                     a.sim.close()
                     used -= a.bytes
