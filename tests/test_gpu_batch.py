@@ -114,3 +114,17 @@ def test_batch_agent_updates_and_errors():
     bad = W.c1(n_a=10, n_b=10)
     with pytest.raises(mabm.MabmError):
         mabm.Batch([models[0], bad])
+
+
+def test_many_tiny_simulations_share_waves():
+    # 40 simulations of 1-120 agents: most waves hold agents of several
+    # simulations, so the per-wave simulation resolution takes many passes;
+    # the split rule makes births of many simulations in one step
+    rng = np.random.default_rng(8)
+    models = []
+    for k in range(40):
+        n = int(rng.integers(1, 121))
+        m = W.c1(n_a=(n + 1) // 2, n_b=n // 2, box_um=0.08 + 0.002 * k, unbind_p=0.05)
+        m.seed = 1000 + k
+        models.append(m)
+    run_batch(models, [1, 2, 5, 20, 60])
