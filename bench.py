@@ -38,15 +38,15 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 # per claimer (q) and per cell of the spatial hash (c) that the kernel must
 # read or write at least once for its function.  An agent is a 16-byte
 # record {x, y, z, species|flags} plus a 4-byte id.
-#   move:    reads record + id (20); writes record (16) and the (cell key,
-#            rank) pair (8)                                          = 44 B/agent
+#   move:    reads record + id (20); writes record (16) and the agent's
+#            rank in its cell (4)                                    = 40 B/agent
 #   scan:    reads the count, writes the start, clears the count     = 12 B/cell
-#   scatter: reads (key, rank), record, id, cell start (32); writes
-#            record, id, claimer byte (21)                           = 53 B/agent
+#   scatter: reads rank, record, id, cell start (28); writes record, id,
+#            claimer byte (21)                                       = 49 B/agent
 #   propose: claimer byte of the chunk (1 B/agent); per claimer its
 #            record and id (20) and its proposal (4)                 = 1 B/agent + 24 B/claimer
 #   finish:  per proposer only (a few hundred per step): counted as 0
-KERNEL_BYTES = {"move": (44, 0, 0), "scan": (0, 0, 12), "scatter": (53, 0, 0),
+KERNEL_BYTES = {"move": (40, 0, 0), "scan": (0, 0, 12), "scatter": (49, 0, 0),
                 "propose": (1, 24, 0), "finish": (0, 0, 0)}
 
 # move is bound by vector-ALU issue, not by HBM: the arithmetic the step

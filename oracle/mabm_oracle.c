@@ -702,7 +702,7 @@ static void phase_move(orc_sim* s, uint32_t i)
         if (reject) { x1 = x; y1 = y; z1 = z; }
     }
     s->mx[i] = x1; s->my[i] = y1; s->mz[i] = z1;
-    s->key[i] = export_key(s, x1, y1, z1);
+    s->key[i] = export_key(s, x1, y1, z1);  /* moved position; placement below may move it */
     s->event[i] = ev;
     s->partner[i] = NONE32;
     s->busy[i] = ev >= 0;
@@ -727,6 +727,7 @@ static void phase_move(orc_sim* s, uint32_t i)
             s->fx[i] = x1 * f; s->fy[i] = y1 * f; s->fz[i] = z1 * f;
         }
         if (ru->p0 >= 0) s->fsp[i] = (uint8_t)ru->p0;
+        s->key[i] = export_key(s, s->fx[i], s->fy[i], s->fz[i]);  /* O6: final position */
         break;
     }
     case ORC_SPLIT:
@@ -737,6 +738,7 @@ static void phase_move(orc_sim* s, uint32_t i)
             s->fx[i] = wrap1(s, s->fx[i]); s->fy[i] = wrap1(s, s->fy[i]); s->fz[i] = wrap1(s, s->fz[i]);
         }
         add_child(s, id, ru->p1, x1 - u[0], y1 - u[1], z1 - u[2]);
+        s->key[i] = export_key(s, s->fx[i], s->fy[i], s->fz[i]);  /* O6: final position */
         break;
     case ORC_EMIT:
         release_offset(s, ru, id, x1, y1, z1, 0, u);

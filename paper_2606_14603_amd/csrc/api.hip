@@ -78,7 +78,7 @@ bool config_ok(const mabm_config* c, std::string& why)
 
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
-    size_t ctl, tab, rec[2], id[2], kr, event, sclaim, cell_count, cell_start, tile_acc, slot,
+    size_t ctl, tab, rec[2], id[2], rank, event, sclaim, cell_count, cell_start, tile_acc, slot,
         prop, plist, rkey, revent, rpartner, births, counts, next_id, total;
     uint32_t ncells, ntiles, tile_shift;
 };
@@ -113,7 +113,7 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
         L.rec[b] = take(cap * 16);
         L.id[b] = take(cap * 4);
     }
-    L.kr = take(cap * 8);
+    L.rank = take(cap * 4);
     L.event = take(cap);
     L.sclaim = take((cap + kClaimChunk - 1) / kClaimChunk * kClaimChunk);
     const size_t padded = (size_t)L.ntiles << (kScanTileLog + L.tile_shift);  // whole scan tiles
@@ -381,7 +381,7 @@ void fill_dev(mabm_sim* s)
         d.a[b].rec = (uint4*)(A + L.rec[b]);
         d.a[b].id = (uint32_t*)(A + L.id[b]);
     }
-    d.kr = (uint2*)(A + L.kr);
+    d.rank = (uint32_t*)(A + L.rank);
     d.event = A + L.event;
     d.sclaim = A + L.sclaim;
     d.cell_count = (uint32_t*)(A + L.cell_count);

@@ -121,7 +121,7 @@ struct Dev {
     Ctl* ctl;
     const Tables* tab;
     Agents a[2];          // ping-pong agent arrays
-    uint2* kr;            // per pre-sort slot: cell key (kNone: not binned), rank in cell
+    uint32_t* rank;       // per pre-sort slot: rank in its cell (kNone: not binned)
     uint8_t* event;       // per pre-sort slot: event rule (record mode)
     uint8_t* sclaim;      // per sorted agent: 1 = claimer this step
     uint32_t* cell_count;  // ncells rounded up to whole scan tiles

@@ -320,7 +320,9 @@ __device__ __forceinline__ void move_agent(const Dev& d, const Tables& T, const 
         }
     }
     if (!dies) {
-        key = cell_of(T, x1, y1, w1);
+        // O6: the cell of the agent's final position (scatter recomputes it
+        // from the record)
+        key = cell_of(T, fx, fy, fz);
         if (B) key += T.cell_base;
         A.rec[i] = make_rec(fx, fy, fz,
                             fs | (ev >= 0 ? kMetaBusy : 0u) | (B ? r.w & kMetaSimMask : 0u));
@@ -361,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
     // rank within the cell, and the per-tile sums the scan starts from
     const uint32_t rank = run_add(key, d.cell_count, 1u);
     run_add(key == kNone ? kNone : key >> (kScanTileLog + d.tile_shift), tile_acc(d, p), kTileStride);
-    if (i < n) d.kr[i] = uint2{key, rank};
+    if (i < n) d.rank[i] = key == kNone ? kNone : rank;
 }
 
 // ---------------------------------------------------------------------------
@@ -582,12 +584,21 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     const uint32_t n = d.ctl->s[p].n_slots;
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const uint2 kr = d.kr[i];
-    if (kr.x == kNone) return;
-    const uint32_t j = d.cell_start[kr.x] + kr.y;
+    const uint32_t rank = d.rank[i];
+    if (rank == kNone) return;
     const Agents A = d.a[p];
     const Agents O = d.a[p ^ 1];
     uint4 r = A.rec[i];
+    // the cell key move binned the agent under, from its recorded position
+    uint32_t key;
+    if (B) {
+        const Tables& Ts = d.tab[sim_of(r.w)];
+        key = Ts.cell_base + cell_of(Ts, __uint_as_float(r.x), __uint_as_float(r.y),
+                                     __uint_as_float(r.z));
+    } else {
+        key = cell_of(T, __uint_as_float(r.x), __uint_as_float(r.y), __uint_as_float(r.z));
+    }
+    const uint32_t j = d.cell_start[key] + rank;
     const bool claim = !(r.w & kMetaBusy) && T.claimer[r.w & 0xFFu];
     if (claim) r.w |= kMetaClaimer;
     O.rec[j] = r;
@@ -596,9 +607,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     if (record) {
         if (B) {
             const Tables& Ts = d.tab[sim_of(r.w)];
-            d.rkey[j] = linear_cell(Ts, kr.x - Ts.cell_base);
+            d.rkey[j] = linear_cell(Ts, key - Ts.cell_base);
         } else {
-            d.rkey[j] = linear_cell(T, kr.x);
+            d.rkey[j] = linear_cell(T, key);
         }
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
