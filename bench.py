@@ -68,9 +68,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
 TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "730fbc079670a9f03ddd5152eb9a9f29c1659aafbd4156070771dd3cf508b6ee",
+           "sources_sha256": "d47152cd0126b73886f5d05400718873b98b98b63bf29a1c3dd424584e8ea3d0",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19679.9, 58998.8), "scan": (4623.8, 16416.1), "scatter": (33143.2, 46321.7), "propose": (19269.8, 2951.9), "finish": (17.7, 0.4)}}
+           "kib": {"move": (19650.6, 51188.8), "scan": (4623.8, 16416.1), "scatter": (28907.2, 46324.4), "propose": (19308.7, 2953.2), "finish": (21.7, 0.4)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
