@@ -44,10 +44,14 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 #   scatter: reads rank, record, id, cell start (28); writes record, id,
 #            claimer byte (21)                                       = 49 B/agent
 #   propose: claimer byte of the chunk (1 B/agent); per claimer its
-#            record and id (20) and its proposal (4)                 = 1 B/agent + 24 B/claimer
+#            record and id (20), its proposal (4), and the search: the
+#            start and end of its 8 stencil cells (64) and the record of
+#            every agent in them (16 each; 8 h^3 x the density expected,
+#            added at run time)                                      = 1 B/agent + 88 B/claimer
+#                                                                      + 16 B/candidate
 #   finish:  per proposer only (a few hundred per step): counted as 0
 KERNEL_BYTES = {"move": (40, 0, 0), "scan": (0, 0, 12), "scatter": (49, 0, 0),
-                "propose": (1, 24, 0), "finish": (0, 0, 0)}
+                "propose": (1, 88, 0), "finish": (0, 0, 0)}
 
 # move is bound by vector-ALU issue, not by HBM: the arithmetic the step
 # definition prescribes per agent (Philox4x32-10 block, event word and
@@ -110,6 +114,12 @@ def copy_ceiling_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
+def volume_um3(model) -> float:
+    if model.geometry == 0:
+        return model.box_um ** 3
+    return 4.0 / 3.0 * 3.141592653589793 * model.outer_radius_um ** 3
 
 
 def describe(model) -> str:
@@ -366,6 +376,8 @@ def main() -> int:
             if launches:
                 a, q, c = KERNEL_BYTES[name]
                 alg = a * live + q * claimers + c * G ** 3
+                if name == "propose":  # candidates: 8 cells at the mean density
+                    alg += 16 * claimers * 8 * h ** 3 * live / volume_um3(model)
                 us = 1e3 * tot / launches
                 kernels[name] = {"launches": launches, "avg_us": round(us, 3),
                                  "alg_bytes": int(alg), "alg_gbs": round(alg / us / 1e3, 1)}
