@@ -5,8 +5,8 @@ unimolecular events and confirmed partners are compared for every live
 agent, id-keyed, at several checkpoints; species counts and the step
 counter are compared too.  Sizes: the C1 workload at full size and horizon,
 scaled C2/C3 models that the oracle finishes in seconds while spanning many
-cells and a ragged tail, and the full 2M-agent C2 and a 1M-agent C3 for a
-few steps in the launch configuration the benchmark times.
+cells and a ragged tail, and the full 2M-agent C2 and 5M-agent C3 for 20
+steps in the launch configuration the benchmark times.
 """
 import numpy as np
 import pytest
@@ -47,12 +47,13 @@ def test_c3_scaled_births_and_translocation():
 
 def test_c2_full_size_in_bench_configuration():
     # the benchmark's configuration: 2M agents, no recording, library-chosen grid
-    run_pair(W.c2(), [1, 3], record=False)
+    run_pair(W.c2(), [1, 3, 20], record=False)
     run_pair(W.c2(), [2], record=True)
 
 
-def test_c3_one_million_few_steps():
-    run_pair(W.c3(1_000_000, seed=314), [1, 4])
+def test_c3_full_size_twenty_steps():
+    # 5M agents in nested compartments with births, at full size
+    run_pair(W.c3(), [1, 20], record=False)
 
 
 def test_ragged_and_tiny_sizes():
