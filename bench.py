@@ -40,6 +40,8 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 # record {x, y, z, species|flags} plus a 4-byte id.
 #   move:    reads record + id (20); writes record (16) and the agent's
 #            rank in its cell (4)                                    = 40 B/agent
+#            in a step that keeps the binning: the claimer byte (1)
+#            instead of the rank                                     = 37 B/agent
 #   scan:    reads the count, writes the start, clears the count     = 12 B/cell
 #   scatter: reads rank, record, id, cell start (28); writes record, id,
 #            claimer byte (21)                                       = 49 B/agent
@@ -50,8 +52,10 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 #            added at run time)                                      = 1 B/agent + 88 B/claimer
 #                                                                      + 16 B/candidate
 #   finish:  per proposer only (a few hundred per step): counted as 0
+#   bookkeep: one workgroup's scalars (a step that keeps the binning): 0
 KERNEL_BYTES = {"move": (40, 0, 0), "scan": (0, 0, 12), "scatter": (49, 0, 0),
-                "propose": (1, 88, 0), "finish": (0, 0, 0)}
+                "propose": (1, 88, 0), "finish": (0, 0, 0), "bookkeep": (0, 0, 0)}
+MOVE_KEPT_BYTES = 37
 
 # move is bound by vector-ALU issue, not by HBM: the arithmetic the step
 # definition prescribes per agent (Philox4x32-10 block, event word and
@@ -372,9 +376,12 @@ def main() -> int:
         ms_direct, _ = timed(args.steps)
         prof = sim.profile_read()
         sim.profile(False)
+        bin_launches = prof["scan"][0]
         for name, (launches, tot) in prof.items():
             if launches:
                 a, q, c = KERNEL_BYTES[name]
+                if name == "move":  # mean over binning and kept steps
+                    a = (a * bin_launches + MOVE_KEPT_BYTES * (launches - bin_launches)) / launches
                 alg = a * live + q * claimers + c * G ** 3
                 if name == "propose":  # candidates: 8 cells at the mean density
                     alg += 16 * claimers * 8 * h ** 3 * live / volume_um3(model)
@@ -402,7 +409,8 @@ def main() -> int:
         roof["traffic"] = kernels[dom].get("traffic_bytes")
         roof["alg_bytes_per_launch"] = kernels[dom]["alg_bytes"]
         roof["hbm_frac_alg_bytes"] = round(kernels[dom]["alg_gbs"] / HBM_PEAK_GBS, 4)
-        step_bytes = sum(k["alg_bytes"] for k in kernels.values())
+        # per step: each kernel's bytes per launch times its launches per step
+        step_bytes = sum(k["alg_bytes"] * k["launches"] for k in kernels.values()) / args.steps
         roof["step_alg_bytes_per_update"] = round(step_bytes / live, 1)
         roof["step_alg_gbs"] = round(step_bytes * args.steps / (ms * 1e-3) / 1e9, 1)
         # the whole step against the HBM roofline of its algorithmic bytes
@@ -416,7 +424,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": describe(model),
                    "agents": model.n_agents, "grid": G, "cell_um": round(h, 5),
-                   "graphs": args.graph, "final_step": t, "tuned_ms_per_step": tuned,
+                   "graphs": args.graph, "bin_every": sim.get_param(mabm.PARAM_BIN_EVERY),
+                   "final_step": t, "tuned_ms_per_step": tuned,
                    "live_agents_end": int(counts.sum())},
         "roofline": roof, "kernels": kernels,
         "ms_per_step_kernel_timed": None if ms_direct is None else ms_direct / args.steps,

@@ -253,6 +253,29 @@ mabm_status mabm_counts_ring(mabm_sim* sim, void* device_ring, uint32_t entries,
 mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
                            uint64_t* n_recorded);
 
+/* Launch-shape parameters of the neighbour search, for tuning (results do
+ * not depend on them).  MABM_PARAM_PROPOSE_LANES: lanes per claimer, 4, 8,
+ * 16 or 32 (0: the library's choice; raised to the least that covers the
+ * stencil with two cells per lane).  MABM_PARAM_PROPOSE_MIN_WORKGROUPS: the
+ * fewest workgroups the search launches, chunks of sorted agents being
+ * shared by up to 16 workgroups to reach it (0: 2048).  Synchronises the
+ * stream; E_INVALID for an unknown parameter or value. */
+#define MABM_PARAM_PROPOSE_LANES 1
+#define MABM_PARAM_PROPOSE_MIN_WORKGROUPS 2
+/* MABM_PARAM_BIN_EVERY_MAX: the most steps between two binnings of the
+ * agents into cells (0: the library's limit, 8; 1: every step).  Between
+ * binnings agents keep their array slots and the neighbour search reads the
+ * last binning's cell lists; the library bins only as rarely as keeps every
+ * result unchanged (every contact radius plus the largest possible Brownian
+ * moves since the binning within the stencil's reach, and never for models
+ * with births or translocations).  Results do not depend on it. */
+#define MABM_PARAM_BIN_EVERY_MAX 3
+/* MABM_PARAM_BIN_EVERY (mabm_get_param only): steps between binnings in
+ * effect (finalizes the model). */
+#define MABM_PARAM_BIN_EVERY 4
+mabm_status mabm_set_param(mabm_sim* sim, int32_t param, uint32_t value);
+mabm_status mabm_get_param(mabm_sim* sim, int32_t param, uint32_t* value);
+
 /* Per-kernel timing: while enabled (1), each step kernel is dispatched with
  * a pair of HIP events that the dispatch itself stamps at the kernel's start
  * and end, so the time is the kernel's own duration; steps then run as

@@ -28,7 +28,11 @@ ABI_VERSION = 1
 FLAG_RECORD = 1
 FLAG_NO_GRAPH = 2
 NONE32 = 0xFFFFFFFF
-N_KERNELS = 5
+N_KERNELS = 6
+PARAM_PROPOSE_LANES = 1
+PARAM_PROPOSE_MIN_WORKGROUPS = 2
+PARAM_BIN_EVERY_MAX = 3
+PARAM_BIN_EVERY = 4
 
 
 class MabmError(RuntimeError):
@@ -92,6 +96,8 @@ def lib() -> ctypes.CDLL:
         L.mabm_ring_entry_bytes.argtypes = [P]
         L.mabm_counts_ring.argtypes = [P, P, c.c_uint32, c.c_uint32]
         L.mabm_ring_read.argtypes = [P, P, c.c_uint32, P]
+        L.mabm_set_param.argtypes = [P, c.c_int32, c.c_uint32]
+        L.mabm_get_param.argtypes = [P, c.c_int32, P]
         L.mabm_last_error.restype = c.c_char_p
         L.mabm_last_error.argtypes = [P]
         for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
@@ -99,7 +105,8 @@ def lib() -> ctypes.CDLL:
                      "mabm_profile", "mabm_profile_read", "mabm_agent_updates",
                      "mabm_destroy_sim", "mabm_create_batch", "mabm_set_initial_counts",
                      "mabm_batch_counts", "mabm_batch_size", "mabm_batch_export",
-                     "mabm_batch_grid", "mabm_counts_ring", "mabm_ring_read"):
+                     "mabm_batch_grid", "mabm_counts_ring", "mabm_ring_read",
+                     "mabm_set_param", "mabm_get_param"):
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -235,6 +242,18 @@ class Sim:
                                           _ptr(launches), _ptr(ms)))
         return {(names[k] or b"kernel%d" % k).decode(): (int(launches[k]), float(ms[k]))
                 for k in range(N_KERNELS)}
+
+    def set_param(self, param: int, value: int):
+        """Performance parameter (PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS,
+        PARAM_BIN_EVERY_MAX); results do not depend on them."""
+        self._chk(lib().mabm_set_param(self._h, int(param), int(value)))
+
+    def get_param(self, param: int) -> int:
+        """A parameter's value; PARAM_BIN_EVERY gives the steps between
+        binnings in effect."""
+        v = ctypes.c_uint32()
+        self._chk(lib().mabm_get_param(self._h, int(param), ctypes.byref(v)))
+        return int(v.value)
 
     def record_counts(self, every: int, entries: int = 4096):
         """Append the live counts to a device ring every ``every`` steps

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -171,9 +172,15 @@ struct mabm_sim {
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
-    // captured steps, per starting parity: one step, and kGraphSteps steps
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    // captured steps (one step, and kGraphSteps steps) per starting state:
+    // parity, agent buffer and steps since the last binning
+    std::map<uint32_t, hipGraphExec_t> graphs;
     int parity = 0;
+    // Binning schedule: the cell lists are rebuilt every `bin_every` steps
+    // (1: every step); `buf` is the agent buffer holding the current state,
+    // `kept` the steps since the last binning (bin_every - 1 forces one)
+    uint32_t bin_every = 1, bin_every_max = 0, kept = 0;
+    int buf = 0;
     uint32_t G = 0;
     float h = 0.0f;
     std::string err;
@@ -370,6 +377,62 @@ mabm_status build_tables(mabm_sim* s)
     return MABM_OK;
 }
 
+// Steps between binnings.  Between two binnings the agents keep their slots
+// and the neighbour search reads the cell lists of the last binning, in
+// which an agent may lie up to k moves away from where it now is.  A step's
+// move along an axis is sigma |z| with |z| < sqrt(-2 ln 2^-24) = 5.768 (the
+// smallest uniform the Box-Muller draw takes is 2^-24; 5.78 leaves room for
+// the approximations of log and cosine), so if every contact radius plus
+// k such moves stays within the stencil's reach (a whole cell for the
+// 27-cell stencil, half a cell for the 8-cell one, less 1 %), every partner
+// within reach is still found and the results are those of binning every
+// step.  Births and translocations put agents far from any cell list, so
+// models with such rules, and models without pair rules, bin every step.
+constexpr uint32_t kMaxBinEvery = 8;
+constexpr double kNormalBound = 5.78;
+
+void set_schedule(mabm_sim* s)
+{
+    uint32_t k = s->bin_every_max ? s->bin_every_max : kMaxBinEvery;
+    bool every = !s->has_bimol;
+    double rmax = 0.0;
+    for (const mabm_rule& u : s->rules) {
+        if (u.kind == MABM_UNIMOL && u.placement != MABM_KEEP) every = true;
+        if (u.kind == MABM_BIMOL) rmax = std::max(rmax, (double)u.radius_um);
+    }
+    double sigma = 0.0;
+    for (int sp = 0; sp < s->tabs[0].ns; ++sp) sigma = std::max(sigma, (double)s->tabs[0].sigma[sp]);
+    const double move = kNormalBound * sigma;
+    if (every) {
+        k = 1;
+    } else if (move > 0.0) {
+        for (uint32_t m = 0; m < s->n_sims; ++m) {
+            const double reach = (s->tabs[m].stencil8 ? 0.5 : 1.0) * (double)s->sim_h[m] * 0.99;
+            const double room = std::max(0.0, std::floor((reach - rmax) / move));
+            k = (uint32_t)std::min((double)k, 1.0 + room);
+        }
+    }
+    s->bin_every = std::max(1u, k);
+    s->kept = s->bin_every - 1;  // the next step bins
+}
+
+// whether the next step bins, given the steps kept since the last binning
+bool bins(const mabm_sim* s, uint32_t kept) { return kept + 1 >= s->bin_every; }
+
+// the device view of the current state (a[parity] = the buffer holding it)
+Dev state_dev(const mabm_sim* s)
+{
+    Dev d = s->dev;
+    d.a[s->parity] = s->dev.a[s->buf];
+    return d;
+}
+
+void drop_graphs(mabm_sim* s)
+{
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    s->graphs.clear();
+}
+
 void fill_dev(mabm_sim* s)
 {
     Dev& d = s->dev;
@@ -446,7 +509,9 @@ mabm_status finalize(mabm_sim* s, bool place)
     HIP_OK(s, hipGetLastError());
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;
+    s->buf = 0;
     s->finalized = true;
+    set_schedule(s);
     return MABM_OK;
 }
 
@@ -458,6 +523,8 @@ mabm_status sync_ctl(mabm_sim* s, Ctl* out)
         s->failed = true;
         if (out->err & kErrPlacement) return fail(s, MABM_E_DEVICE, "initial placement failed after 64 attempts");
         if (out->err & kErrBirths) return fail(s, MABM_E_CAPACITY, "more than 4096 births in one step");
+        if (out->err & kErrKeptBinning)
+            return fail(s, MABM_E_DEVICE, "births in a step that kept the previous binning");
         return fail(s, MABM_E_CAPACITY, "agent capacity exceeded by births");
     }
     return MABM_OK;
@@ -465,7 +532,7 @@ mabm_status sync_ctl(mabm_sim* s, Ctl* out)
 
 mabm_status live_counts(mabm_sim* s, std::vector<unsigned long long>& out, Ctl* ctl)
 {
-    launch_counts(s->dev, s->parity, s->stream);
+    launch_counts(state_dev(s), s->parity, s->stream);
     HIP_OK(s, hipGetLastError());
     out.assign((size_t)kMaxSpecies * s->n_sims, 0ull);
     HIP_OK(s, hipMemcpyAsync(out.data(), s->dev.counts, out.size() * 8, hipMemcpyDeviceToHost,
@@ -671,33 +738,72 @@ mabm_status mabm_grid(mabm_sim* s, uint32_t* g, float* h)
 
 namespace {
 
-// one step of parity p: move, scan, scatter, [propose, finish]
-void enqueue_step(mabm_sim* s, int p)
+// one step of parity p on the agents in buffer `buf`: move, then scan and
+// scatter into the other buffer (bin) or the bookkeeping of a step that
+// keeps the cell lists, then [propose, finish]
+void enqueue_step(mabm_sim* s, int p, int buf, bool bin)
 {
-    const Dev& d = s->dev;
+    Dev d = s->dev;
+    d.a[p] = s->dev.a[buf];
+    d.a[p ^ 1] = s->dev.a[bin ? buf ^ 1 : buf];
     const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
     hipStream_t q = s->stream;
-    timed(s, kKMove, [&](const KEvents& e) { launch_move(d, p, rec, q, e); });
-    timed(s, kKScan, [&](const KEvents& e) { launch_scan(d, p, q, e); });
-    timed(s, kKScatter, [&](const KEvents& e) { launch_scatter(d, p, rec, q, e); });
+    timed(s, kKMove, [&](const KEvents& e) { launch_move(d, p, rec, bin ? 1 : 0, q, e); });
+    if (bin) {
+        timed(s, kKScan, [&](const KEvents& e) { launch_scan(d, p, q, e); });
+        timed(s, kKScatter, [&](const KEvents& e) { launch_scatter(d, p, rec, q, e); });
+    } else {
+        timed(s, kKBookkeep, [&](const KEvents& e) { launch_bookkeep(d, p, q, e); });
+    }
     if (s->has_bimol) {
         timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, q, e); });
         timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, q, e); });
     }
 }
 
-// Capture `steps` consecutive steps starting at parity cur as one graph on
+// Capture `steps` consecutive steps from the current schedule state as one graph on
 // the caller's stream (kernel nodes only: the step has no memset or copy).
 // Long runs replay the multi-step graph, so the host issues one launch per
 // kGraphSteps steps; that matters for small simulations, whose steps take
 // about as long to enqueue as to run.
 constexpr uint32_t kGraphSteps = 16;
 
-mabm_status capture(mabm_sim* s, int cur, uint32_t steps, hipGraphExec_t* out)
+// Advances the schedule state (parity, buffer, steps kept) by one step;
+// returns whether that step bins.
+bool advance(mabm_sim* s)
+{
+    const bool bin = bins(s, s->kept);
+    s->parity ^= 1;
+    if (bin) {
+        s->buf ^= 1;
+        s->kept = 0;
+    } else {
+        ++s->kept;
+    }
+    return bin;
+}
+
+// Enqueues `steps` steps from the current schedule state and advances it.
+void enqueue_steps(mabm_sim* s, uint32_t steps)
+{
+    for (uint32_t k = 0; k < steps; ++k) {
+        const int p = s->parity, b = s->buf;
+        const bool bin = advance(s);
+        enqueue_step(s, p, b, bin);
+    }
+}
+
+mabm_status capture(mabm_sim* s, uint32_t steps, hipGraphExec_t* out)
 {
     hipGraph_t g = nullptr;
+    // the schedule state is restored: the graph is launched after capture
+    const int parity = s->parity, buf = s->buf;
+    const uint32_t kept = s->kept;
     HIP_OK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-    for (uint32_t k = 0; k < steps; ++k) enqueue_step(s, cur ^ int(k & 1u));
+    enqueue_steps(s, steps);
+    s->parity = parity;
+    s->buf = buf;
+    s->kept = kept;
     HIP_OK(s, hipStreamEndCapture(s->stream, &g));
     const hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -719,30 +825,33 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
     const bool graphs = s->stream != nullptr && !s->prof && !(s->cfg.flags & MABM_FLAG_NO_GRAPH);
     uint32_t k = 0;
     while (k < n_steps) {
-        const int cur = s->parity;
         uint32_t m = 1;
         // steps until the next counts-ring entry (a graph never spans one)
         const uint64_t until_rec =
             s->ring_every ? s->ring_every - s->steps_done % s->ring_every : ~0ull;
         if (graphs) {
-            const int kind = (n_steps - k >= kGraphSteps && until_rec >= kGraphSteps) ? 1 : 0;
+            const uint32_t kind = (n_steps - k >= kGraphSteps && until_rec >= kGraphSteps) ? 1 : 0;
             m = kind ? kGraphSteps : 1u;
-            hipGraphExec_t& g = s->graph[cur][kind];
+            const uint32_t key = kind | uint32_t(s->parity) << 1 | uint32_t(s->buf) << 2 | s->kept << 3;
+            hipGraphExec_t& g = s->graphs[key];
             if (!g) {
-                st = capture(s, cur, m, &g);
-                if (st != MABM_OK) return st;
+                st = capture(s, m, &g);
+                if (st != MABM_OK) {
+                    s->graphs.erase(key);
+                    return st;
+                }
             }
             HIP_OK(s, hipGraphLaunch(g, s->stream));
+            for (uint32_t j = 0; j < m; ++j) advance(s);  // the state the graph leaves
         } else {
-            enqueue_step(s, cur);
+            enqueue_steps(s, 1);
         }
-        s->parity = cur ^ int(m & 1u);
         s->steps_done += m;
         k += m;
         if (s->ring_every && s->steps_done % s->ring_every == 0) {
             unsigned long long* e =
                 s->ring + (s->ring_recorded % s->ring_entries) * ring_words(s);
-            launch_counts(s->dev, s->parity, s->stream, e + 1, e);
+            launch_counts(state_dev(s), s->parity, s->stream, e + 1, e);
             ++s->ring_recorded;
         }
     }
@@ -802,7 +911,7 @@ mabm_status export_impl(mabm_sim* s, uint32_t sim, uint32_t capacity, uint32_t* 
     st = sync_ctl(s, &ctl);
     if (st != MABM_OK) return st;
     const uint32_t n_slots = ctl.s[s->parity].n_slots;
-    const Agents& A = s->dev.a[s->parity];
+    const Agents& A = s->dev.a[s->buf];
     // slot ranges that can hold the simulation's agents: all slots for a
     // single simulation; in a batch, its initial block before any step, and
     // after one its cells' run of the cell-sorted array plus the last step's
@@ -916,6 +1025,8 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
     HIP_OK(s, hipMemcpyAsync(s->dev.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;
+    s->buf = 0;
+    s->kept = s->bin_every - 1;  // imported agents are not binned
     return MABM_OK;
 }
 
@@ -1044,6 +1155,51 @@ mabm_status mabm_ring_read(mabm_sim* s, uint64_t* out, uint32_t max_entries, uin
     return MABM_OK;
 }
 
+mabm_status mabm_set_param(mabm_sim* s, int32_t param, uint32_t value)
+{
+    if (!s) return MABM_E_INVALID;
+    // captured steps hold the old launch shape and schedule
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    drop_graphs(s);
+    switch (param) {
+    case MABM_PARAM_PROPOSE_LANES: {
+        // a power of two that covers the stencil with at most two cells per lane
+        const bool ok = value == 0 || value == 4 || value == 8 || value == 16 || value == 32;
+        if (!ok) return fail(s, MABM_E_INVALID, "lanes per claimer must be 0, 4, 8, 16 or 32");
+        s->dev.prop_lanes = value;
+        return MABM_OK;
+    }
+    case MABM_PARAM_PROPOSE_MIN_WORKGROUPS:
+        if (value > (1u << 20)) return fail(s, MABM_E_INVALID, "at most 2^20 workgroups");
+        s->dev.prop_min_blocks = value;
+        return MABM_OK;
+    case MABM_PARAM_BIN_EVERY_MAX:
+        if (value > kMaxBinEvery) return fail(s, MABM_E_INVALID, "at most 8 steps between binnings");
+        s->bin_every_max = value;
+        if (s->finalized) set_schedule(s);
+        return MABM_OK;
+    default:
+        return fail(s, MABM_E_INVALID, "unknown parameter");
+    }
+}
+
+mabm_status mabm_get_param(mabm_sim* s, int32_t param, uint32_t* value)
+{
+    if (!s || !value) return MABM_E_INVALID;
+    switch (param) {
+    case MABM_PARAM_PROPOSE_LANES: *value = s->dev.prop_lanes; return MABM_OK;
+    case MABM_PARAM_PROPOSE_MIN_WORKGROUPS: *value = s->dev.prop_min_blocks; return MABM_OK;
+    case MABM_PARAM_BIN_EVERY_MAX: *value = s->bin_every_max; return MABM_OK;
+    case MABM_PARAM_BIN_EVERY: {
+        mabm_status st = finalize(s, true);
+        if (st != MABM_OK) return st;
+        *value = s->bin_every;
+        return MABM_OK;
+    }
+    default: return fail(s, MABM_E_INVALID, "unknown parameter");
+    }
+}
+
 mabm_status mabm_agent_updates(mabm_sim* s, uint64_t* out)
 {
     if (!s || !out) return MABM_E_INVALID;
@@ -1060,9 +1216,7 @@ mabm_status mabm_destroy_sim(mabm_sim* s)
 {
     if (!s) return MABM_E_INVALID;
     (void)hipStreamSynchronize(s->stream);
-    for (auto& per_parity : s->graph)
-        for (hipGraphExec_t& g : per_parity)
-            if (g) (void)hipGraphExecDestroy(g);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (EventPair& p : s->pool) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);

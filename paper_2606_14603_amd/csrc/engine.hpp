@@ -49,7 +49,7 @@ enum Geometry : int32_t { kBox = 0, kSphere = 1, kNested = 2 };
 enum Placement : int32_t { kKeep = 0, kSplit = 1, kEmit = 2, kTranslocate = 3 };
 
 // sticky device error bits
-enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u };
+enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u, kErrKeptBinning = 8u };
 
 struct RuleDev {
     int32_t kind, placement, p0, p1, to;
@@ -102,7 +102,11 @@ struct Ctl {
     uint32_t n_births[2];  // birth records appended by the step of parity p
     uint32_t holes[2];     // agents consumed by pair rules in the step of parity p
     uint32_t n_prop[2];    // entries of the proposer list of the step of parity p
-    uint32_t n_binned;     // agents binned in the current step
+    uint32_t n_binned;     // agents binned in the current step (all slots in a step
+                           // that keeps the previous binning)
+    uint32_t uni_dead[2];  // agents removed by unimolecular rules in the step of parity p
+    uint32_t dead_base;    // holes at the step's start older than the previous step's
+                           // pair rules (steps that keep the binning compact nothing)
     uint32_t err;          // ErrBit, sticky
     unsigned long long agent_updates;  // sum of live agents at step starts
 };
@@ -140,10 +144,14 @@ struct Dev {
     uint32_t capacity, ncells, ntiles, n_init;
     uint32_t tile_shift;         // a scan tile is kScanTile << tile_shift cells
     uint32_t n_sims;             // 1: a single simulation; tab has n_sims entries
+    // launch shape of the neighbour search (performance only; results do
+    // not depend on them): lanes per claimer (0: 4 for the 8-cell stencil,
+    // 16 for the 27-cell one) and the fewest workgroups to launch
+    uint32_t prop_lanes, prop_min_blocks;
 };
 
 // kernel indices for per-kernel timing
-enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kNumKernels };
+enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kKBookkeep, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 // Optional start/stop events of a step kernel: when set, the dispatch itself
@@ -155,12 +163,18 @@ struct KEvents {
 
 // launch entry points (kernels.hip); each enqueues one kernel on `s`
 void launch_init(const Dev& d, hipStream_t s);
-// p: parity of the step (its agents start in a[p] and are sorted into a[p ^ 1])
-void launch_move(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
+// p: parity of the step (its agents start in a[p] and are sorted into
+// a[p ^ 1]; for a step that keeps the binning the caller maps both to the
+// buffer that holds the agents)
+// bin = 0: the step keeps the previous step's cell lists (agents stay in
+// their slots; move then sets the claimer flags and marks its removals as
+// holes, and launch_bookkeep replaces scan and scatter)
+void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev = {});
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
 void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
+void launch_bookkeep(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 // per-(simulation, species) live counts into d.counts, or into dst (same
 // layout) with the step counter in *tslot (a counts-ring entry)
 void launch_counts(const Dev& d, int cur, hipStream_t s, unsigned long long* dst = nullptr,

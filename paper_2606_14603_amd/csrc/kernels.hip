@@ -39,7 +39,8 @@
 
 namespace mabm {
 
-const char* const kKernelNames[kNumKernels] = {"move", "scan", "scatter", "propose", "finish"};
+const char* const kKernelNames[kNumKernels] = {"move",    "scan",   "scatter",
+                                               "propose", "finish", "bookkeep"};
 
 namespace {
 
@@ -221,10 +222,13 @@ __device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent,
 // unimolecular part of O8, then the cell key of the moved position and the
 // agent's rank within its cell.
 // ---------------------------------------------------------------------------
-// One live agent's step up to its cell key (the body of move).
+// One live agent's step up to its cell key (the body of move).  In a step
+// that keeps the previous binning (bin = 0) the agent stays in slot i, so
+// its claimer flag and recorded fields are written here instead of by
+// scatter.  Returns whether a unimolecular rule removed the agent.
 template <bool B>
-__device__ __forceinline__ void move_agent(const Dev& d, const Tables& T, const Agents& A, int p,
-                                           int record, uint32_t i, uint32_t id, uint32_t t,
+__device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const Agents& A, int p,
+                                           int record, int bin, uint32_t i, uint32_t id, uint32_t t,
                                            const uint4& r, uint32_t s, uint32_t& key)
 {
     const float x = __uint_as_float(r.x), y = __uint_as_float(r.y), z = __uint_as_float(r.z);
@@ -319,19 +323,36 @@ __device__ __forceinline__ void move_agent(const Dev& d, const Tables& T, const 
         }
         }
     }
-    if (!dies) {
+    const uint32_t sim_bits = B ? r.w & kMetaSimMask : 0u;
+    if (dies) {
+        // a hole until the next binning drops it
+        A.rec[i].w = uint32_t(kDead) | sim_bits;
+        if (!bin) d.sclaim[i] = 0;
+        return true;
+    }
+    const uint32_t meta = fs | (ev >= 0 ? kMetaBusy : 0u) | sim_bits;
+    if (bin) {
         // O6: the cell of the agent's final position (scatter recomputes it
         // from the record)
         key = cell_of(T, fx, fy, fz);
         if (B) key += T.cell_base;
-        A.rec[i] = make_rec(fx, fy, fz,
-                            fs | (ev >= 0 ? kMetaBusy : 0u) | (B ? r.w & kMetaSimMask : 0u));
+        A.rec[i] = make_rec(fx, fy, fz, meta);
         if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
+    } else {
+        const bool claim = ev < 0 && T.claimer[fs];
+        A.rec[i] = make_rec(fx, fy, fz, meta | (claim ? kMetaClaimer : 0u));
+        d.sclaim[i] = claim ? 1 : 0;
+        if (record) {
+            d.rkey[i] = linear_cell(T, cell_of(T, fx, fy, fz));
+            d.revent[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
+            d.rpartner[i] = kNone;
+        }
     }
+    return false;
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
+__global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int bin)
 {
     const uint32_t n = d.ctl->s[p].n_slots;
     const uint32_t t = d.ctl->s[p].t;
@@ -352,14 +373,22 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record)
         id = A.id[i];
     }
     const uint32_t s = r.w & 0xFFu;
+    bool died = false;
     if (s != kDead) {
         if (B)
             per_sim(sim_of(r.w), [&](uint32_t u) {
-                move_agent<true>(d, d.tab[u], A, p, record, i, id, t, r, s, key);
+                died = move_agent<true>(d, d.tab[u], A, p, record, bin, i, id, t, r, s, key);
             });
         else
-            move_agent<false>(d, *d.tab, A, p, record, i, id, t, r, s, key);
+            died = move_agent<false>(d, *d.tab, A, p, record, bin, i, id, t, r, s, key);
+    } else if (!bin && i < n) {
+        d.sclaim[i] = 0;  // a hole kept in its slot
     }
+    // removals, for the count of live agents (one atomic per wave that has any)
+    const uint64_t gone = __ballot(died);
+    if (gone && lane_id() == __ffsll((long long)gone) - 1)
+        atomicAdd(&d.ctl->uni_dead[p], uint32_t(__popcll(gone)));
+    if (!bin) return;
     // rank within the cell, and the per-tile sums the scan starts from
     const uint32_t rank = run_add(key, d.cell_count, 1u);
     run_add(key == kNone ? kNone : key >> (kScanTileLog + d.tile_shift), tile_acc(d, p), kTileStride);
@@ -558,9 +587,12 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
     }
     if (threadIdx.x == 0) {
         if (err) atomicOr(&ctl->err, err);
-        // live agents at this step's start: its slots minus the holes the
-        // previous step's pair rules left in them
-        ctl->agent_updates += cur.n_slots - ctl->holes[p ^ 1];
+        // live agents at this step's start: its slots minus the holes in
+        // them (the previous step's pair rules', and any older ones kept by
+        // steps that did not bin); the binning has dropped them all
+        ctl->agent_updates += cur.n_slots - ctl->dead_base - ctl->holes[p ^ 1];
+        ctl->dead_base = 0u;
+        ctl->uni_dead[p] = 0u;
         ctl->holes[p ^ 1] = 0u;
         ctl->n_births[p ^ 1] = 0u;
         ctl->n_prop[p ^ 1] = 0u;
@@ -613,6 +645,34 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
         }
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bookkeeping of a step that keeps the previous step's cell lists (in place
+// of scan and scatter; one workgroup): nothing is binned or compacted, every
+// slot stays a search candidate slot, holes are carried to the next step,
+// and the scan's clearing of the other parity's tile sums is done here.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_bookkeep(Dev d, int p)
+{
+    Ctl* ctl = d.ctl;
+    uint32_t* acc = tile_acc(d, p ^ 1);
+    for (uint32_t k = threadIdx.x; k < d.ntiles; k += kBlock) acc[size_t(k) * kTileStride] = 0u;
+    if (threadIdx.x == 0) {
+        const StepState cur = ctl->s[p];
+        const uint32_t prev_holes = ctl->holes[p ^ 1];
+        ctl->n_binned = cur.n_slots;
+        ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
+        ctl->dead_base += prev_holes + ctl->uni_dead[p];
+        ctl->uni_dead[p] = 0u;
+        ctl->holes[p ^ 1] = 0u;
+        ctl->n_births[p ^ 1] = 0u;
+        ctl->n_prop[p ^ 1] = 0u;
+        // such a step has no births (the library keeps the binning only for
+        // models without birth or translocation rules)
+        if (ctl->n_births[p]) atomicOr(&ctl->err, kErrKeptBinning);
+        ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots, cur.next_id, 0u};
     }
 }
 
@@ -862,9 +922,11 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
     const uint32_t nl = compact_claimers(word, first, last, list, &count);
-    // a subgroup of `width` lanes per claimer, two stencil cells per lane
-    // (the stencil is the same for every simulation of a batch)
-    const int width = T.stencil8 ? 4 : 16;
+    // a subgroup of `width` lanes per claimer, at most two stencil cells
+    // per lane (the stencil is the same for every simulation of a batch)
+    // (never fewer lanes than cover the stencil with two cells each)
+    const int wmin = T.stencil8 ? 4 : 16;
+    const int width = int(d.prop_lanes) > wmin ? int(d.prop_lanes) : wmin;
     const int ncell = T.stencil8 ? 8 : 27;
     const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
     const int nsub = kBlock / width;
@@ -1000,7 +1062,7 @@ __global__ void k_zero_counts(Dev d, int cur, unsigned long long* tslot)
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(uint32_t n) { return n ? (n + kBlock - 1) / kBlock : 1u; }
 static constexpr unsigned kFinishBlocks = 64;
-static constexpr unsigned kPropMinBlocks = 2048;
+static constexpr unsigned kPropMinBlocks = 2048;  // default fewest propose workgroups
 static inline unsigned chunks_for(uint32_t n) { return n ? (n + kPChunk - 1) / kPChunk : 1u; }
 
 void launch_init(const Dev& d, hipStream_t s)
@@ -1020,10 +1082,14 @@ static inline void go(K kernel, unsigned grid, unsigned block, hipStream_t s, co
 
 // the batch variants of the agent kernels (template argument true) resolve
 // each agent's simulation; a single simulation takes the plain ones
-void launch_move(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
+void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {
-    if (d.n_sims > 1) go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
-    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record);
+    if (d.n_sims > 1) go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
+    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
+}
+void launch_bookkeep(const Dev& d, int p, hipStream_t s, const KEvents& ev)
+{
+    go(k_bookkeep, 1u, kBlock, s, ev, d, p);
 }
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
@@ -1040,7 +1106,8 @@ void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev)
     // enough workgroups to fill the chip: chunks shared by up to 16
     const unsigned chunks = chunks_for(d.capacity);
     unsigned split = 1;
-    while (split < 16 && chunks * split * 2 <= kPropMinBlocks) split *= 2;
+    const unsigned min_blocks = d.prop_min_blocks ? d.prop_min_blocks : kPropMinBlocks;
+    while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
     if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split);
     else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split);
 }

@@ -9,18 +9,25 @@ tuner times a few steps of the model at each candidate grid, from the same
 initial state, and keeps the fastest; results are cached per (geometry,
 agents, density, largest contact radius), so models of one shape are tuned
 once.
+
+At the chosen cell size the tuner then times the neighbour search's launch
+shape, also a pure performance choice: lanes per claimer (each lane scans at
+most two stencil cells, so more lanes mean shorter, more parallel searches
+and fewer claimers per wave) and the fewest workgroups the search launches
+(chunks of sorted agents shared by more workgroups fill the chip at small
+agent counts, at the price of re-reading the chunk's claim flags).
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-from dataclasses import dataclass
-from typing import Dict, List, Optional
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
 
 from . import Sim
 
-_CACHE: Dict[str, float] = {}
+_CACHE: Dict[str, dict] = {}
 
 
 def _extent(m) -> float:
@@ -69,34 +76,69 @@ class TuneResult:
     cell_um: float
     ms_per_step: Dict[float, float]
     cached: bool = False
+    lanes: int = 0              # 0: the library's choice
+    min_workgroups: int = 0     # 0: the library's choice
+    ms_per_shape: Dict[Tuple[int, int], float] = field(default_factory=dict)
+
+    def apply(self, sim) -> None:
+        """Set the tuned launch shape on a simulation built at ``cell_um``."""
+        from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+        sim.set_param(PARAM_PROPOSE_LANES, self.lanes)
+        sim.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, self.min_workgroups)
 
 
-def tune_cell(model, steps: int = 20, warm: int = 5, cache_path: Optional[str] = None) -> TuneResult:
-    """Fastest cell size for ``model`` among ``candidates`` (ms per step
-    measured with HIP events on each candidate's stream)."""
+def shapes(cell_um: float, model) -> List[Tuple[int, int]]:
+    """Launch shapes to try: the default, twice the default lanes, and
+    fewer or more workgroups."""
+    ext, rmax = _extent(model), _rmax(model)
+    g = int(ext / cell_um)
+    stencil8 = rmax > 0 and ext / g >= 2.02 * rmax
+    lanes = 4 if stencil8 else 16
+    return [(0, 0), (2 * lanes, 0), (0, 512), (0, 8192)]
+
+
+def _time(model, cell_um: float, shape: Tuple[int, int], steps: int, warm: int) -> float:
     import torch
+    from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+    sim = Sim(model, cell_um=cell_um)
+    sim.set_param(PARAM_PROPOSE_LANES, shape[0])
+    sim.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, shape[1])
+    sim.step(warm)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    sim.close()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_cell(model, steps: int = 20, warm: int = 5, cache_path: Optional[str] = None,
+              launch_shape: bool = True) -> TuneResult:
+    """Fastest cell size for ``model`` among ``candidates``, then (with
+    ``launch_shape``) the fastest neighbour-search launch shape among
+    ``shapes`` at that cell size; ms per step measured with HIP events on
+    each trial's stream."""
     key = shape_key(model)
     if cache_path and not _CACHE and os.path.exists(cache_path):
         with open(cache_path) as f:
             _CACHE.update(json.load(f))
     if key in _CACHE:
-        return TuneResult(_CACHE[key], {}, cached=True)
-    timings = {}
-    for h in candidates(model):
-        sim = Sim(model, cell_um=h)
-        sim.step(warm)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        sim.step(steps)
-        e1.record(sim.stream)
-        torch.cuda.synchronize()
-        timings[h] = e0.elapsed_time(e1) / steps
-        sim.close()
+        c = _CACHE[key]
+        if isinstance(c, dict):
+            return TuneResult(c["cell_um"], {}, True, c.get("lanes", 0), c.get("min_workgroups", 0))
+        return TuneResult(float(c), {}, cached=True)
+    timings = {h: _time(model, h, (0, 0), steps, warm) for h in candidates(model)}
     best = min(timings, key=timings.get)
-    _CACHE[key] = best
+    per_shape = {(0, 0): timings[best]}
+    if launch_shape:
+        for sh in shapes(best, model)[1:]:
+            per_shape[sh] = _time(model, best, sh, steps, warm)
+    lanes, minwg = min(per_shape, key=per_shape.get)
+    _CACHE[key] = {"cell_um": best, "lanes": lanes, "min_workgroups": minwg}
     if cache_path:
         with open(cache_path, "w") as f:
             json.dump(_CACHE, f, indent=1, sort_keys=True)
-    return TuneResult(best, timings)
+    return TuneResult(best, timings, False, lanes, minwg, per_shape)

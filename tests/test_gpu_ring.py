@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import run_pair, say
+from parity import assert_same, run_pair, say
 
 pytestmark = pytest.mark.gpu
 
@@ -92,5 +92,43 @@ def test_tuner_picks_a_candidate_and_caches_it(tmp_path):
     m = W.c2(60_000, seed=3)
     r = tune.tune_cell(m, steps=5, warm=2, cache_path=str(tmp_path / "cells.json"))
     assert r.cell_um in r.ms_per_step and len(r.ms_per_step) == len(tune.candidates(m))
-    assert tune.tune_cell(W.c2(60_000, seed=4)).cached
-    say(f"[tune] {m.name}: {r.cell_um:.4f} um from {r.ms_per_step}")
+    assert (r.lanes, r.min_workgroups) in r.ms_per_shape
+    assert set(r.ms_per_shape) == set(tune.shapes(r.cell_um, m))
+    c = tune.tune_cell(W.c2(60_000, seed=4))
+    assert c.cached and (c.cell_um, c.lanes, c.min_workgroups) == (r.cell_um, r.lanes,
+                                                                   r.min_workgroups)
+    say(f"[tune] {m.name}: {r.cell_um:.4f} um from {r.ms_per_step}, "
+        f"shape {r.lanes, r.min_workgroups} from {r.ms_per_shape}")
+
+
+@pytest.mark.parametrize("which", ["c2_27cell", "c2_8cell", "c3", "box"])
+def test_launch_shape_leaves_results_unchanged(which):
+    # lanes per claimer and the propose split change only how the search is
+    # spread over lanes and workgroups: exports stay bit-identical to the
+    # oracle's, also when the shape changes between graph-replayed steps
+    import paper_2606_14603_amd as mabm
+    if which.startswith("c2"):
+        m = W.c2(50_000, seed=21, steps=40)
+        rmax = max(r.radius_um for r in m.rules if r.kind == W.BIMOL)
+        cell = 1.5 * rmax if which == "c2_27cell" else 2.05 * rmax
+    elif which == "c3":
+        m, cell = W.c3(15_000, seed=22, n_genes=200), None
+    else:
+        m, cell = W.c1(n_a=3000, n_b=2500, box_um=0.5, unbind_p=2e-2), None
+    shapes = [(32, 0), (4, 1 << 16), (8, 1), (16, 512), (0, 0)]
+    g = mabm.Sim(m, record=True, cell_um=cell, graphs=True)
+    G, _ = g.grid()
+    o = oracle.OracleSim(m, grid_n=G)
+    for k, (lanes, minwg) in enumerate(shapes):
+        g.set_param(mabm.PARAM_PROPOSE_LANES, lanes)
+        g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, minwg)
+        g.step(8 + k)
+        o.step(8 + k)
+        assert_same(g.export(), o.export(), f"{m.name} shape {lanes, minwg}")
+    with pytest.raises(mabm.MabmError):
+        g.set_param(mabm.PARAM_PROPOSE_LANES, 3)
+    with pytest.raises(mabm.MabmError):
+        g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, (1 << 20) + 1)
+    with pytest.raises(mabm.MabmError):
+        g.set_param(99, 0)
+    say(f"[shape] {which} G={G} ok")
