@@ -52,9 +52,8 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 #            added at run time)                                      = 1 B/agent + 88 B/claimer
 #                                                                      + 16 B/candidate
 #   finish:  per proposer only (a few hundred per step): counted as 0
-#   bookkeep: one workgroup's scalars (a step that keeps the binning): 0
 KERNEL_BYTES = {"move": (40, 0, 0), "scan": (0, 0, 12), "scatter": (49, 0, 0),
-                "propose": (1, 88, 0), "finish": (0, 0, 0), "bookkeep": (0, 0, 0)}
+                "propose": (1, 88, 0), "finish": (0, 0, 0)}
 MOVE_KEPT_BYTES = 37
 
 # move is bound by vector-ALU issue, not by HBM: the arithmetic the step

@@ -28,7 +28,7 @@ ABI_VERSION = 1
 FLAG_RECORD = 1
 FLAG_NO_GRAPH = 2
 NONE32 = 0xFFFFFFFF
-N_KERNELS = 6
+N_KERNELS = 5
 PARAM_PROPOSE_LANES = 1
 PARAM_PROPOSE_MIN_WORKGROUPS = 2
 PARAM_BIN_EVERY_MAX = 3

@@ -738,9 +738,9 @@ mabm_status mabm_grid(mabm_sim* s, uint32_t* g, float* h)
 
 namespace {
 
-// one step of parity p on the agents in buffer `buf`: move, then scan and
-// scatter into the other buffer (bin) or the bookkeeping of a step that
-// keeps the cell lists, then [propose, finish]
+// one step of parity p on the agents in buffer `buf`: move, scan and
+// scatter into the other buffer (bin; a step that keeps the cell lists has
+// neither), then [propose, finish]
 void enqueue_step(mabm_sim* s, int p, int buf, bool bin)
 {
     Dev d = s->dev;
@@ -752,12 +752,12 @@ void enqueue_step(mabm_sim* s, int p, int buf, bool bin)
     if (bin) {
         timed(s, kKScan, [&](const KEvents& e) { launch_scan(d, p, q, e); });
         timed(s, kKScatter, [&](const KEvents& e) { launch_scatter(d, p, rec, q, e); });
-    } else {
-        timed(s, kKBookkeep, [&](const KEvents& e) { launch_bookkeep(d, p, q, e); });
     }
+    // (only models with pair rules keep cell lists)
     if (s->has_bimol) {
-        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, q, e); });
-        timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, q, e); });
+        const int b = bin ? 1 : 0;
+        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, b, q, e); });
+        timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, b, q, e); });
     }
 }
 

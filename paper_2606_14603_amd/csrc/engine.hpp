@@ -151,7 +151,7 @@ struct Dev {
 };
 
 // kernel indices for per-kernel timing
-enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kKBookkeep, kNumKernels };
+enum KernelId { kKMove = 0, kKScan, kKScatter, kKPropose, kKFinish, kNumKernels };
 extern const char* const kKernelNames[kNumKernels];
 
 // Optional start/stop events of a step kernel: when set, the dispatch itself
@@ -168,13 +168,12 @@ void launch_init(const Dev& d, hipStream_t s);
 // buffer that holds the agents)
 // bin = 0: the step keeps the previous step's cell lists (agents stay in
 // their slots; move then sets the claimer flags and marks its removals as
-// holes, and launch_bookkeep replaces scan and scatter)
+// holes, there is no scan or scatter, and finish does the bookkeeping)
 void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev = {});
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
-void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
-void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
-void launch_bookkeep(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
+void launch_propose(const Dev& d, int p, int bin, hipStream_t s, const KEvents& ev = {});
+void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev = {});
 // per-(simulation, species) live counts into d.counts, or into dst (same
 // layout) with the step counter in *tslot (a counts-ring entry)
 void launch_counts(const Dev& d, int cur, hipStream_t s, unsigned long long* dst = nullptr,

@@ -22,6 +22,12 @@
 //            Bernoulli draw; handshake keys into both claim slots
 //   finish   per chunk: confirmation and pair products
 //
+// A step that keeps the previous binning (the library allows it while no
+// agent can have moved out of reach of the cell lists it was binned in) is
+// move, propose and finish on the agents in place: move also writes the
+// claimer flags and marks removed agents as holes, and finish's first
+// workgroup does the step's bookkeeping.
+//
 // Cells are sorted by the Morton index of their coordinates, so the cells of
 // a neighbourhood are close in memory.  An agent is a 16-byte record
 // {x, y, z, meta} plus a 4-byte id, so a
@@ -39,8 +45,7 @@
 
 namespace mabm {
 
-const char* const kKernelNames[kNumKernels] = {"move",    "scan",   "scatter",
-                                               "propose", "finish", "bookkeep"};
+const char* const kKernelNames[kNumKernels] = {"move", "scan", "scatter", "propose", "finish"};
 
 namespace {
 
@@ -649,12 +654,13 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 }
 
 // ---------------------------------------------------------------------------
-// bookkeeping of a step that keeps the previous step's cell lists (in place
-// of scan and scatter; one workgroup): nothing is binned or compacted, every
-// slot stays a search candidate slot, holes are carried to the next step,
-// and the scan's clearing of the other parity's tile sums is done here.
+// bookkeeping of a step that keeps the previous step's cell lists (there is
+// no scan or scatter; run by the first workgroup of finish, after the
+// search): nothing was binned or compacted, holes are carried to the next
+// step, and the scan's clearing of the other parity's tile sums is done
+// here.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_bookkeep(Dev d, int p)
+__device__ void kept_bookkeeping(const Dev& d, int p)
 {
     Ctl* ctl = d.ctl;
     uint32_t* acc = tile_acc(d, p ^ 1);
@@ -883,7 +889,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split)
+__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split, int bin)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t plocal[kPChunk];
@@ -902,7 +908,9 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
     // control block).
     const uint32_t word =
         *reinterpret_cast<const FlagWord*>(d.sclaim + first + uint32_t(kClaimPer) * threadIdx.x);
-    const uint32_t n = d.ctl->n_binned;
+    // claimers among the binned agents; a step that keeps the binning
+    // searches from every slot
+    const uint32_t n = bin ? d.ctl->n_binned : d.ctl->s[p].n_slots;
     const uint32_t t = d.ctl->s[p].t;
     if (first >= n) return;
     {
@@ -957,11 +965,12 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
 // which another thread may be testing, is never rewritten.
 // ---------------------------------------------------------------------------
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record)
+__global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int bin)
 {
     __shared__ uint32_t s_holes;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
+    if (!bin && blockIdx.x == 0) kept_bookkeeping(d, p);
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
     if (blockIdx.x * kBlock >= np) return;
@@ -1087,10 +1096,7 @@ void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const 
     if (d.n_sims > 1) go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
     else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
 }
-void launch_bookkeep(const Dev& d, int p, hipStream_t s, const KEvents& ev)
-{
-    go(k_bookkeep, 1u, kBlock, s, ev, d, p);
-}
+
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
     go(k_scan, d.ntiles, kScanThreads, s, ev, d, p);
@@ -1101,23 +1107,23 @@ void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvent
     if (d.n_sims > 1) go(k_scatter<true>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
     else go(k_scatter<false>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
 }
-void launch_propose(const Dev& d, int p, hipStream_t s, const KEvents& ev)
+void launch_propose(const Dev& d, int p, int bin, hipStream_t s, const KEvents& ev)
 {
     // enough workgroups to fill the chip: chunks shared by up to 16
     const unsigned chunks = chunks_for(d.capacity);
     unsigned split = 1;
     const unsigned min_blocks = d.prop_min_blocks ? d.prop_min_blocks : kPropMinBlocks;
     while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
-    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split);
-    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split);
+    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin);
+    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin);
 }
-void launch_finish(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
+void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {
     // a fixed grid strides over the step's proposer list
     unsigned nb = blocks_for(d.capacity);
     if (nb > kFinishBlocks) nb = kFinishBlocks;
-    if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record);
-    else go(k_finish<false>, nb, kBlock, s, ev, d, p, record);
+    if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record, bin);
+    else go(k_finish<false>, nb, kBlock, s, ev, d, p, record, bin);
 }
 void launch_counts(const Dev& d0, int cur, hipStream_t s, unsigned long long* dst,
                    unsigned long long* tslot)
