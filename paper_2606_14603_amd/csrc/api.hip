@@ -255,6 +255,32 @@ void timed(mabm_sim* s, int kid, F&& launch)
     launch(KEvents{p.a, p.b});
 }
 
+// Steps between binnings.  Between two binnings the agents keep their slots
+// and the neighbour search reads the cell lists of the last binning, in
+// which an agent may lie up to k moves away from where it now is.  A step's
+// move along an axis is sigma |z| with |z| < sqrt(-2 ln 2^-24) = 5.768 (the
+// smallest uniform the Box-Muller draw takes is 2^-24; 5.78 leaves room for
+// the approximations of log and cosine), so if every contact radius plus
+// k such moves stays within the stencil's reach (a whole cell for the
+// 27-cell stencil, half a cell for the 8-cell one, less 1 %), every partner
+// within reach is still found and the results are those of binning every
+// step.  Births and translocations put agents far from any cell list, so
+// models with such rules, and models without pair rules, bin every step.
+constexpr uint32_t kMaxBinEvery = 8;
+constexpr double kNormalBound = 5.78;
+
+// whether the model allows keeping cell lists at all: it has pair rules
+// (else nothing searches them) and no births or translocations
+bool may_keep_binning(const mabm_sim* s)
+{
+    bool bimol = false;
+    for (const mabm_rule& u : s->rules) {
+        if (u.kind == MABM_UNIMOL && u.placement != MABM_KEEP) return false;
+        if (u.kind == MABM_BIMOL) bimol = true;
+    }
+    return bimol;
+}
+
 // tables of simulation k of s (the only one, or one of a batch)
 mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
 {
@@ -339,6 +365,16 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
         G = (uint32_t)std::floor(ext / (1.01 * rmax));
         if (G < 3) return fail(s, MABM_E_INVALID, "volume smaller than 3 cells of the contact radius");
     }
+    // Default grid: if cells up to 10 % larger let the 8-cell stencil's cell
+    // lists be kept for a step, take them (in a batch the fewest steps any
+    // simulation allows decide for all).
+    if (c.cell_um <= 0.0f && rmax > 0.0 && may_keep_binning(s)) {
+        double move = 0.0;
+        for (int k = 0; k < ns; ++k) move = std::max(move, kNormalBound * (double)T.sigma[k]);
+        const double need = (rmax + move) / (0.5 * 0.99) * (1.0 + 1e-6);
+        if (ext / G < need && need <= 1.1 * ext / G)
+            G = std::max(3u, (uint32_t)std::floor(ext / need));
+    }
     s->sim_G[k_sim] = G;
     s->sim_h[k_sim] = (float)(ext / G);
     T.G = G;
@@ -377,29 +413,13 @@ mabm_status build_tables(mabm_sim* s)
     return MABM_OK;
 }
 
-// Steps between binnings.  Between two binnings the agents keep their slots
-// and the neighbour search reads the cell lists of the last binning, in
-// which an agent may lie up to k moves away from where it now is.  A step's
-// move along an axis is sigma |z| with |z| < sqrt(-2 ln 2^-24) = 5.768 (the
-// smallest uniform the Box-Muller draw takes is 2^-24; 5.78 leaves room for
-// the approximations of log and cosine), so if every contact radius plus
-// k such moves stays within the stencil's reach (a whole cell for the
-// 27-cell stencil, half a cell for the 8-cell one, less 1 %), every partner
-// within reach is still found and the results are those of binning every
-// step.  Births and translocations put agents far from any cell list, so
-// models with such rules, and models without pair rules, bin every step.
-constexpr uint32_t kMaxBinEvery = 8;
-constexpr double kNormalBound = 5.78;
-
 void set_schedule(mabm_sim* s)
 {
     uint32_t k = s->bin_every_max ? s->bin_every_max : kMaxBinEvery;
-    bool every = !s->has_bimol;
+    const bool every = !may_keep_binning(s);
     double rmax = 0.0;
-    for (const mabm_rule& u : s->rules) {
-        if (u.kind == MABM_UNIMOL && u.placement != MABM_KEEP) every = true;
+    for (const mabm_rule& u : s->rules)
         if (u.kind == MABM_BIMOL) rmax = std::max(rmax, (double)u.radius_um);
-    }
     double sigma = 0.0;
     for (int sp = 0; sp < s->tabs[0].ns; ++sp) sigma = std::max(sigma, (double)s->tabs[0].sigma[sp]);
     const double move = kNormalBound * sigma;

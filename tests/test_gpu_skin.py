@@ -174,3 +174,19 @@ def test_ring_over_kept_steps():
     steps, counts = g.ring()
     assert list(steps) == list(range(3, 37, 3))
     assert np.array_equal(counts[:, 0, :], np.array(want))
+
+
+def test_default_grid_is_coarsened_to_keep_binning():
+    # 95k agents at the cascade's density: the power-of-two grid (64 per
+    # axis) has cells just too small to keep the cell lists for a step; the
+    # default takes the 63-cell grid instead, and the results stay exact
+    import paper_2606_14603_amd as mabm
+    m = W.c2(95_000, seed=40, steps=60)
+    g = mabm.Sim(m, record=True)
+    G, _ = g.grid()
+    assert G == 63
+    assert g.get_param(mabm.PARAM_BIN_EVERY) == expected_bin_every(m, G) == 2
+    o = oracle.OracleSim(m, grid_n=G)
+    g.step(9)
+    o.step(9)
+    assert_same(g.export(), o.export(), "coarsened default grid")
