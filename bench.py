@@ -75,9 +75,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
 TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "d47152cd0126b73886f5d05400718873b98b98b63bf29a1c3dd424584e8ea3d0",
+           "sources_sha256": "9cb0c4a80b0de92630a6bcde147a8b8b69f54d5e10b2e36bf0b6181c4e4ab741",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19650.6, 51188.8), "scan": (4623.8, 16416.1), "scatter": (28907.2, 46324.4), "propose": (19308.7, 2953.2), "finish": (21.7, 0.4)}}
+           "kib": {"move": (19625.5, 44040.7), "scan": (4630.2, 16416.1), "scatter": (30773.7, 49733.7), "propose": (18826.0, 2951.6), "finish": (25.6, 16.2)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
@@ -387,7 +387,7 @@ def main() -> int:
                 us = 1e3 * tot / launches
                 kernels[name] = {"launches": launches, "avg_us": round(us, 3),
                                  "alg_bytes": int(alg), "alg_gbs": round(alg / us / 1e3, 1)}
-                tb = measured_traffic(name) if args.workload == "c2" and live > 1.9e6 else None
+                tb = measured_traffic(name) if args.workload == "c2" and args.agents == 2_000_000 else None
                 if tb is not None:
                     kernels[name]["traffic_bytes"] = tb
                     kernels[name]["traffic_gbs"] = round(tb / us / 1e3, 1)
