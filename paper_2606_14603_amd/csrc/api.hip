@@ -180,6 +180,7 @@ struct mabm_sim {
     // (1: every step); `buf` is the agent buffer holding the current state,
     // `kept` the steps since the last binning (bin_every - 1 forces one)
     uint32_t bin_every = 1, bin_every_max = 0, kept = 0;
+    float move_um = 0.0f;  // bound on one step's move along an axis
     int buf = 0;
     uint32_t G = 0;
     float h = 0.0f;
@@ -331,6 +332,7 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             T.rule_of[u.reactant[0]][u.reactant[1]] = (int8_t)r;
             T.claimer[u.reactant[0]] = 1;
             T.claim_r2max[u.reactant[0]] = std::max(T.claim_r2max[u.reactant[0]], R.r2);
+            T.claim_rmax[u.reactant[0]] = std::max(T.claim_rmax[u.reactant[0]], u.radius_um);
             rmax = std::max(rmax, (double)u.radius_um);
             s->has_bimol = true;
         }
@@ -423,6 +425,7 @@ void set_schedule(mabm_sim* s)
     double sigma = 0.0;
     for (int sp = 0; sp < s->tabs[0].ns; ++sp) sigma = std::max(sigma, (double)s->tabs[0].sigma[sp]);
     const double move = kNormalBound * sigma;
+    s->move_um = (float)move;
     if (every) {
         k = 1;
     } else if (move > 0.0) {
@@ -761,7 +764,7 @@ namespace {
 // one step of parity p on the agents in buffer `buf`: move, scan and
 // scatter into the other buffer (bin; a step that keeps the cell lists has
 // neither), then [propose, finish]
-void enqueue_step(mabm_sim* s, int p, int buf, bool bin)
+void enqueue_step(mabm_sim* s, int p, int buf, bool bin, float stale)
 {
     Dev d = s->dev;
     d.a[p] = s->dev.a[buf];
@@ -776,7 +779,7 @@ void enqueue_step(mabm_sim* s, int p, int buf, bool bin)
     // (only models with pair rules keep cell lists)
     if (s->has_bimol) {
         const int b = bin ? 1 : 0;
-        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, b, q, e); });
+        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, b, stale, q, e); });
         timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, b, q, e); });
     }
 }
@@ -808,8 +811,9 @@ void enqueue_steps(mabm_sim* s, uint32_t steps)
 {
     for (uint32_t k = 0; k < steps; ++k) {
         const int p = s->parity, b = s->buf;
+        const uint32_t moved = s->kept + 1;  // moves since the binning, if this step keeps it
         const bool bin = advance(s);
-        enqueue_step(s, p, b, bin);
+        enqueue_step(s, p, b, bin, bin ? 0.0f : (float)moved * s->move_um);
     }
 }
 

@@ -754,6 +754,7 @@ struct PairLds {
     int8_t rule_of[kMaxSpecies * kMaxSpecies];
     float r2[kMaxRules];
     float r2max[kMaxSpecies];  // per claimer species, its largest r2
+    float rmax[kMaxSpecies];   // and its largest contact radius
 };
 
 __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, const Agents& A,
@@ -809,7 +810,7 @@ template <bool B>
 __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, const PairLds& P,
                                                const Agents& A, uint32_t t, uint32_t j,
                                                const uint4& rj, int li, int width, int ncell,
-                                               uint32_t* plocal, uint32_t* nprop)
+                                               float stale, uint32_t* plocal, uint32_t* nprop)
 {
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
@@ -824,25 +825,39 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         c[a] = int(cell_coord(T, pp[a]));
         f[a] = (pp[a] - T.lo) * T.inv_h - float(c[a]);
     }
-    // candidate range of stencil cell m (empty outside the grid)
+    // Stencil cells that cannot hold a partner are not read.  Per axis, the
+    // gap from the claimer to the cell (in cells; 0 along an axis where the
+    // cell is level with the claimer's own), less how far a candidate may
+    // have moved since it was binned, gives a lower bound on the distance to
+    // any candidate listed in the cell; the cell is skipped when that bound
+    // exceeds the claimer's largest contact radius, padded by 0.1 % and
+    // 1e-3 cells (far above the rounding of the cell coordinates).
+    const float moved = stale * T.inv_h;
+    const float rho = P.rmax[s] * T.inv_h * 1.001f + 1e-3f;
+    const float rho2 = rho * rho;
+    // candidate range of stencil cell m (empty outside the grid or out of reach)
     auto range = [&](int m, uint32_t& lo, uint32_t& hi) {
         lo = hi = 0;
         if (m >= ncell) return;
         int cc[3];
+        float gap2 = 0.0f;
         for (int a = 0; a < 3; ++a) {
-            int v;
+            int o;
             if (T.stencil8) {
                 // the neighbour on the side of the cell the point is nearer
-                const int bit = (m >> a) & 1;
-                v = c[a] + bit * (f[a] < 0.5f ? -1 : 1);
+                o = ((m >> a) & 1) * (f[a] < 0.5f ? -1 : 1);
             } else {
-                const int o = a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9);
-                v = c[a] + o - 1;
+                o = (a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9)) - 1;
             }
+            float g = o < 0 ? f[a] : (o > 0 ? 1.0f - f[a] : 0.0f);
+            g = fmaxf(g - moved, 0.0f);
+            gap2 += g * g;
+            int v = c[a] + o;
             if (periodic) v = (v + G) % G;
             else if (v < 0 || v >= G) return;
             cc[a] = v;
         }
+        if (gap2 > rho2) return;
         uint32_t cell = cell_key(uint32_t(cc[0]), uint32_t(cc[1]), uint32_t(cc[2]));
         if (B) cell += T.cell_base;
         lo = d.cell_start[cell];
@@ -889,7 +904,8 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split, int bin)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_propose(Dev d, int p, uint32_t split, int bin, float stale)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t plocal[kPChunk];
@@ -920,7 +936,10 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
         uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
         for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
         for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
-        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kBlock) P.r2max[q] = T.claim_r2max[q];
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kBlock) {
+            P.r2max[q] = T.claim_r2max[q];
+            P.rmax[q] = T.claim_rmax[q];
+        }
         if (threadIdx.x == 0) {
             nprop = 0;
             count = 0;
@@ -943,10 +962,11 @@ __global__ void __launch_bounds__(kBlock) k_propose(Dev d, int p, uint32_t split
         const uint4 rj = A.rec[j];
         if (B)
             per_sim(sim_of(rj.w), [&](uint32_t u) {
-                search_claimer<true>(d, d.tab[u], P, A, t, j, rj, li, width, ncell, plocal, &nprop);
+                search_claimer<true>(d, d.tab[u], P, A, t, j, rj, li, width, ncell, stale, plocal,
+                                     &nprop);
             });
         else
-            search_claimer<false>(d, T, P, A, t, j, rj, li, width, ncell, plocal, &nprop);
+            search_claimer<false>(d, T, P, A, t, j, rj, li, width, ncell, stale, plocal, &nprop);
     }
     // the workgroup's proposers join the step's proposer list (one global
     // atomic per workgroup that has any)
@@ -1107,15 +1127,15 @@ void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvent
     if (d.n_sims > 1) go(k_scatter<true>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
     else go(k_scatter<false>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
 }
-void launch_propose(const Dev& d, int p, int bin, hipStream_t s, const KEvents& ev)
+void launch_propose(const Dev& d, int p, int bin, float stale, hipStream_t s, const KEvents& ev)
 {
     // enough workgroups to fill the chip: chunks shared by up to 16
     const unsigned chunks = chunks_for(d.capacity);
     unsigned split = 1;
     const unsigned min_blocks = d.prop_min_blocks ? d.prop_min_blocks : kPropMinBlocks;
     while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
-    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin);
-    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin);
+    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin, stale);
+    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin, stale);
 }
 void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {
