@@ -180,7 +180,6 @@ struct mabm_sim {
     // (1: every step); `buf` is the agent buffer holding the current state,
     // `kept` the steps since the last binning (bin_every - 1 forces one)
     uint32_t bin_every = 1, bin_every_max = 0, kept = 0;
-    float move_um = 0.0f;  // bound on one step's move along an axis
     int buf = 0;
     uint32_t G = 0;
     float h = 0.0f;
@@ -258,15 +257,20 @@ void timed(mabm_sim* s, int kid, F&& launch)
 
 // Steps between binnings.  Between two binnings the agents keep their slots
 // and the neighbour search reads the cell lists of the last binning, in
-// which an agent may lie up to k moves away from where it now is.  A step's
+// which an agent may lie up to j moves away from where it now is.  A step's
 // move along an axis is sigma |z| with |z| < sqrt(-2 ln 2^-24) = 5.768 (the
 // smallest uniform the Box-Muller draw takes is 2^-24; 5.78 leaves room for
-// the approximations of log and cosine), so if every contact radius plus
-// k such moves stays within the stencil's reach (a whole cell for the
-// 27-cell stencil, half a cell for the 8-cell one, less 1 %), every partner
-// within reach is still found and the results are those of binning every
-// step.  Births and translocations put agents far from any cell list, so
-// models with such rules, and models without pair rules, bin every step.
+// the approximations of log and cosine), sigma being that of the agent's
+// species at the time, so a target of a claimer's rules moves at most
+// claim_dmax per step (the largest bound over every species that is, or can
+// turn into, such a target).  While a claimer species' largest contact
+// radius plus j such moves stays within its stencil's reach (half a cell
+// for the 8-cell stencil, a whole cell for the 27-cell one, less 1 %),
+// every partner within reach is still found and the results are those of
+// binning every step; a claimer species whose reach outgrows the 8-cell
+// stencil searches 27 cells in the later kept steps.  Births and
+// translocations put agents far from any cell list, so models with such
+// rules, and models without pair rules, bin every step.
 constexpr uint32_t kMaxBinEvery = 8;
 constexpr double kNormalBound = 5.78;
 
@@ -309,6 +313,19 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
         T.sigma[k] = (float)std::sqrt(2.0 * (double)s->species[k].D * (double)c.dt_s);
     }
     if (acc > c.capacity) return fail(s, MABM_E_CAPACITY, "initial counts exceed the capacity");
+    // species x can become species y (the same agent): through a
+    // conversion, or as a pair rule's claimer or target product
+    bool becomes[kMaxSpecies][kMaxSpecies] = {};
+    for (int k = 0; k < ns; ++k) becomes[k][k] = true;
+    for (const mabm_rule& u : s->rules) {
+        if (u.reactant[0] >= 0 && u.product[0] >= 0) becomes[u.reactant[0]][u.product[0]] = true;
+        if (u.kind == MABM_BIMOL && u.reactant[1] >= 0 && u.product[1] >= 0)
+            becomes[u.reactant[1]][u.product[1]] = true;
+    }
+    for (int m = 0; m < ns; ++m)
+        for (int a = 0; a < ns; ++a)
+            for (int b = 0; b < ns; ++b)
+                if (becomes[a][m] && becomes[m][b]) becomes[a][b] = true;
     for (int a = 0; a < kMaxSpecies; ++a)
         for (int b = 0; b < kMaxSpecies; ++b) T.rule_of[a][b] = -1;
     double rmax = 0.0;
@@ -333,6 +350,10 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             T.claimer[u.reactant[0]] = 1;
             T.claim_r2max[u.reactant[0]] = std::max(T.claim_r2max[u.reactant[0]], R.r2);
             T.claim_rmax[u.reactant[0]] = std::max(T.claim_rmax[u.reactant[0]], u.radius_um);
+            for (int k = 0; k < ns; ++k)
+                if (becomes[k][u.reactant[1]])
+                    T.claim_dmax[u.reactant[0]] =
+                        std::max(T.claim_dmax[u.reactant[0]], (float)(kNormalBound * (double)T.sigma[k]));
             rmax = std::max(rmax, (double)u.radius_um);
             s->has_bimol = true;
         }
@@ -366,16 +387,6 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             return fail(s, MABM_E_INVALID, "cell_um smaller than 1.01 x the largest contact radius");
         G = (uint32_t)std::floor(ext / (1.01 * rmax));
         if (G < 3) return fail(s, MABM_E_INVALID, "volume smaller than 3 cells of the contact radius");
-    }
-    // Default grid: if cells up to 10 % larger let the 8-cell stencil's cell
-    // lists be kept for a step, take them (in a batch the fewest steps any
-    // simulation allows decide for all).
-    if (c.cell_um <= 0.0f && rmax > 0.0 && may_keep_binning(s)) {
-        double move = 0.0;
-        for (int k = 0; k < ns; ++k) move = std::max(move, kNormalBound * (double)T.sigma[k]);
-        const double need = (rmax + move) / (0.5 * 0.99) * (1.0 + 1e-6);
-        if (ext / G < need && need <= 1.1 * ext / G)
-            G = std::max(3u, (uint32_t)std::floor(ext / need));
     }
     s->sim_G[k_sim] = G;
     s->sim_h[k_sim] = (float)(ext / G);
@@ -415,24 +426,47 @@ mabm_status build_tables(mabm_sim* s)
     return MABM_OK;
 }
 
+// whether claimer species sp needs the 27-cell stencil in some step of a
+// binning kept for k steps, in any simulation
+bool needs_wide(const mabm_sim* s, int sp, uint32_t k)
+{
+    for (uint32_t m = 0; m < s->n_sims; ++m) {
+        const Tables& T = s->tabs[m];
+        const double req = (double)T.claim_rmax[sp] + (double)(k - 1) * (double)T.claim_dmax[sp];
+        if (!T.stencil8 || req > 0.5 * 0.99 * (double)s->sim_h[m]) return true;
+    }
+    return false;
+}
+
 void set_schedule(mabm_sim* s)
 {
     uint32_t k = s->bin_every_max ? s->bin_every_max : kMaxBinEvery;
-    const bool every = !may_keep_binning(s);
-    double rmax = 0.0;
-    for (const mabm_rule& u : s->rules)
-        if (u.kind == MABM_BIMOL) rmax = std::max(rmax, (double)u.radius_um);
-    double sigma = 0.0;
-    for (int sp = 0; sp < s->tabs[0].ns; ++sp) sigma = std::max(sigma, (double)s->tabs[0].sigma[sp]);
-    const double move = kNormalBound * sigma;
-    s->move_um = (float)move;
-    if (every) {
-        k = 1;
-    } else if (move > 0.0) {
-        for (uint32_t m = 0; m < s->n_sims; ++m) {
-            const double reach = (s->tabs[m].stencil8 ? 0.5 : 1.0) * (double)s->sim_h[m] * 0.99;
-            const double room = std::max(0.0, std::floor((reach - rmax) / move));
-            k = (uint32_t)std::min((double)k, 1.0 + room);
+    if (!may_keep_binning(s)) k = 1;
+    const Tables& T0 = s->tabs[0];
+    // every claimer species' reach within the 27-cell stencil's
+    for (uint32_t m = 0; m < s->n_sims; ++m)
+        for (int sp = 0; sp < T0.ns; ++sp) {
+            const double dmax = T0.claim_dmax[sp];
+            if (!T0.claimer[sp] || dmax <= 0.0) continue;
+            const double room = std::floor((0.99 * (double)s->sim_h[m] - (double)T0.claim_rmax[sp]) / dmax);
+            k = (uint32_t)std::min((double)k, 1.0 + std::max(0.0, room));
+        }
+    // A claimer searches about three times the cells with the 27-cell
+    // stencil: where the grid allows the 8-cell one, keep a binning longer
+    // only while the claimer species that would need 27 cells hold at most
+    // an eighth of the initial claimers.
+    if (T0.stencil8) {
+        while (k > 1) {
+            uint64_t all = 0, wide = 0;
+            for (int sp = 0; sp < T0.ns; ++sp) {
+                if (!T0.claimer[sp]) continue;
+                uint64_t n = 0;
+                for (uint32_t m = 0; m < s->n_sims; ++m) n += s->sim_counts[sp][m];
+                all += n;
+                if (needs_wide(s, sp, k)) wide += n;
+            }
+            if (8 * wide <= all) break;
+            --k;
         }
     }
     s->bin_every = std::max(1u, k);
@@ -764,14 +798,14 @@ namespace {
 // one step of parity p on the agents in buffer `buf`: move, scan and
 // scatter into the other buffer (bin; a step that keeps the cell lists has
 // neither), then [propose, finish]
-void enqueue_step(mabm_sim* s, int p, int buf, bool bin, float stale)
+void enqueue_step(mabm_sim* s, int p, int buf, bool bin, uint32_t moved)
 {
     Dev d = s->dev;
     d.a[p] = s->dev.a[buf];
     d.a[p ^ 1] = s->dev.a[bin ? buf ^ 1 : buf];
     const int rec = (s->cfg.flags & MABM_FLAG_RECORD) ? 1 : 0;
     hipStream_t q = s->stream;
-    timed(s, kKMove, [&](const KEvents& e) { launch_move(d, p, rec, bin ? 1 : 0, q, e); });
+    timed(s, kKMove, [&](const KEvents& e) { launch_move(d, p, rec, bin ? 1 : 0, moved, q, e); });
     if (bin) {
         timed(s, kKScan, [&](const KEvents& e) { launch_scan(d, p, q, e); });
         timed(s, kKScatter, [&](const KEvents& e) { launch_scatter(d, p, rec, q, e); });
@@ -779,7 +813,7 @@ void enqueue_step(mabm_sim* s, int p, int buf, bool bin, float stale)
     // (only models with pair rules keep cell lists)
     if (s->has_bimol) {
         const int b = bin ? 1 : 0;
-        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, b, stale, q, e); });
+        timed(s, kKPropose, [&](const KEvents& e) { launch_propose(d, p, b, moved, q, e); });
         timed(s, kKFinish, [&](const KEvents& e) { launch_finish(d, p, rec, b, q, e); });
     }
 }
@@ -813,7 +847,7 @@ void enqueue_steps(mabm_sim* s, uint32_t steps)
         const int p = s->parity, b = s->buf;
         const uint32_t moved = s->kept + 1;  // moves since the binning, if this step keeps it
         const bool bin = advance(s);
-        enqueue_step(s, p, b, bin, bin ? 0.0f : (float)moved * s->move_um);
+        enqueue_step(s, p, b, bin, bin ? 0u : moved);
     }
 }
 

@@ -80,6 +80,9 @@ struct Tables {
     uint8_t claimer[kMaxSpecies];
     float claim_r2max[kMaxSpecies];  // largest squared contact radius of a claimer's rules
     float claim_rmax[kMaxSpecies];   // and that radius (um)
+    // per claimer species: how far (um, along an axis) one step can move any
+    // agent that is, or can later become, a target of its rules
+    float claim_dmax[kMaxSpecies];
     uint8_t uni_n[kMaxSpecies][2];
     uint8_t uni_rule[kMaxSpecies][2][kMaxUni];
     uint64_t uni_thr[kMaxSpecies][2][kMaxUni];
@@ -170,12 +173,13 @@ void launch_init(const Dev& d, hipStream_t s);
 // bin = 0: the step keeps the previous step's cell lists (agents stay in
 // their slots; move then sets the claimer flags and marks its removals as
 // holes, there is no scan or scatter, and finish does the bookkeeping)
-void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev = {});
+void launch_move(const Dev& d, int p, int record, int bin, uint32_t moved, hipStream_t s,
+                 const KEvents& ev = {});
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev = {});
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev = {});
-// stale: how far (um, along an axis) an agent may have moved since it was
-// binned (0 in a binning step)
-void launch_propose(const Dev& d, int p, int bin, float stale, hipStream_t s, const KEvents& ev = {});
+// moved: steps since the agents were binned (0 in a binning step)
+void launch_propose(const Dev& d, int p, int bin, uint32_t moved, hipStream_t s,
+                    const KEvents& ev = {});
 void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev = {});
 // per-(simulation, species) live counts into d.counts, or into dst (same
 // layout) with the step counter in *tslot (a counts-ring entry)

@@ -228,13 +228,16 @@ __device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent,
 // agent's rank within its cell.
 // ---------------------------------------------------------------------------
 // One live agent's step up to its cell key (the body of move).  In a step
-// that keeps the previous binning (bin = 0) the agent stays in slot i, so
-// its claimer flag and recorded fields are written here instead of by
-// scatter.  Returns whether a unimolecular rule removed the agent.
+// that keeps the previous binning (bin = 0, `moved` steps after it) the
+// agent stays in slot i, so its claimer flag (2 if its species searches the
+// 27-cell stencil this step, as the search decides) and recorded fields are
+// written here instead of by scatter.  Returns whether a unimolecular rule
+// removed the agent.
 template <bool B>
 __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const Agents& A, int p,
-                                           int record, int bin, uint32_t i, uint32_t id, uint32_t t,
-                                           const uint4& r, uint32_t s, uint32_t& key)
+                                           int record, int bin, uint32_t moved, uint32_t i,
+                                           uint32_t id, uint32_t t, const uint4& r, uint32_t s,
+                                           uint32_t& key)
 {
     const float x = __uint_as_float(r.x), y = __uint_as_float(r.y), z = __uint_as_float(r.z);
     const int c0 = compartment(T, x, y, z);
@@ -345,8 +348,10 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
         if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
     } else {
         const bool claim = ev < 0 && T.claimer[fs];
+        const bool wide =
+            T.stencil8 && (T.claim_rmax[fs] + float(moved) * T.claim_dmax[fs]) * T.inv_h > 0.495f;
         A.rec[i] = make_rec(fx, fy, fz, meta | (claim ? kMetaClaimer : 0u));
-        d.sclaim[i] = claim ? 1 : 0;
+        d.sclaim[i] = claim ? (wide ? 2 : 1) : 0;
         if (record) {
             d.rkey[i] = linear_cell(T, cell_of(T, fx, fy, fz));
             d.revent[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
@@ -357,7 +362,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int bin)
+__global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int bin, uint32_t moved)
 {
     const uint32_t n = d.ctl->s[p].n_slots;
     const uint32_t t = d.ctl->s[p].t;
@@ -382,10 +387,10 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int b
     if (s != kDead) {
         if (B)
             per_sim(sim_of(r.w), [&](uint32_t u) {
-                died = move_agent<true>(d, d.tab[u], A, p, record, bin, i, id, t, r, s, key);
+                died = move_agent<true>(d, d.tab[u], A, p, record, bin, moved, i, id, t, r, s, key);
             });
         else
-            died = move_agent<false>(d, *d.tab, A, p, record, bin, i, id, t, r, s, key);
+            died = move_agent<false>(d, *d.tab, A, p, record, bin, moved, i, id, t, r, s, key);
     } else if (!bin && i < n) {
         d.sclaim[i] = 0;  // a hole kept in its slot
     }
@@ -683,19 +688,23 @@ __device__ void kept_bookkeeping(const Dev& d, int p)
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
-// kPChunk = kClaimPer x kBlock sorted agents, in agent order: each thread
-// reads the claimer flags of its kClaimPer agents as one word, a wave-level
-// prefix places them within the wave, and the waves' totals, exchanged
-// through LDS, place the waves.  The order is the same in every workgroup
-// that compacts the chunk, which lets several share its claimers.  `word`
-// is loaded by the caller before anything else so that its latency
-// overlaps the kernel's other set-up loads.  Returns the list length.
+// kPChunk = kClaimPer x kBlock sorted agents: each thread reads the claimer
+// flags of its kClaimPer agents as one word (1: a claimer, 2: a claimer that
+// searches the 27-cell stencil this step), a wave-level prefix of both
+// counts places them within the wave, and the waves' totals, exchanged
+// through LDS, place the waves; the wide claimers come first, each kind in
+// agent order.  The order is the same in every workgroup that compacts the
+// chunk, which lets several share its claimers.  `word` is loaded by the
+// caller before anything else so that its latency overlaps the kernel's
+// other set-up loads.  Returns the list length, and the wide claimers'
+// count in *n_wide.
 constexpr int kClaimPer = kPChunk / kBlock;
 static_assert(kClaimPer == 2 || kClaimPer == 4, "two or four claimer flags per thread");
 using FlagWord = std::conditional_t<kClaimPer == 4, uint32_t, uint16_t>;
 
 __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t first, uint32_t last,
-                                                     uint32_t* list, uint32_t* count)
+                                                     uint32_t* list, uint32_t* count,
+                                                     uint32_t* n_wide)
 {
     const uint32_t k0 = first + uint32_t(kClaimPer) * threadIdx.x;
     uint32_t flags = 0;
@@ -705,9 +714,13 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
         const uint32_t valid = last - k0;
         if (valid < uint32_t(kClaimPer)) flags &= (1u << (8u * valid)) - 1u;
     }
+    // counts packed as (wide << 16) | narrow (each at most kPChunk)
     uint32_t mine = 0;
 #pragma unroll
-    for (int b = 0; b < kClaimPer; ++b) mine += (flags >> (8 * b)) & 0xFFu ? 1u : 0u;
+    for (int b = 0; b < kClaimPer; ++b) {
+        const uint32_t v = (flags >> (8 * b)) & 0xFFu;
+        mine += v == 2u ? 0x10000u : (v ? 1u : 0u);
+    }
     uint32_t incl = mine;
     const int lane = lane_id();
 #pragma unroll
@@ -725,12 +738,20 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
         if (k < wv) base += wsum[k];
         total += wsum[k];
     }
+    const uint32_t tw = total >> 16, tn = total & 0xFFFFu;
+    uint32_t bw = base >> 16, bn = tw + (base & 0xFFFFu);
 #pragma unroll
-    for (int b = 0; b < kClaimPer; ++b)
-        if ((flags >> (8 * b)) & 0xFFu) list[base++] = k0 + uint32_t(b);
-    if (threadIdx.x == 0) *count = total;
+    for (int b = 0; b < kClaimPer; ++b) {
+        const uint32_t v = (flags >> (8 * b)) & 0xFFu;
+        if (v == 2u) list[bw++] = k0 + uint32_t(b);
+        else if (v) list[bn++] = k0 + uint32_t(b);
+    }
+    if (threadIdx.x == 0) {
+        *count = tw + tn;
+        *n_wide = tw;
+    }
     __syncthreads();
-    return total;
+    return tw + tn;
 }
 
 // ---------------------------------------------------------------------------
@@ -755,6 +776,7 @@ struct PairLds {
     float r2[kMaxRules];
     float r2max[kMaxSpecies];  // per claimer species, its largest r2
     float rmax[kMaxSpecies];   // and its largest contact radius
+    float dmax[kMaxSpecies];   // and how far one step moves its targets at most
 };
 
 __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, const Agents& A,
@@ -788,33 +810,46 @@ __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, cons
     }
 }
 
-// Lexicographic minimum of (d^2, id) over the lanes of a subgroup of
-// `width` lanes (xor butterfly within the subgroup).
-__device__ __forceinline__ void reduce_best(Best& b, int width)
+// Lexicographic minimum of (d^2, id) over the lanes of each aligned group
+// of w lanes (xor butterfly; w differs between groups of one wave, so the
+// exchange runs over the widest group's steps, `top`, and a lane combines
+// only steps within its own group).
+__device__ __forceinline__ void reduce_best(Best& b, int w, int top)
 {
-    for (int o = width >> 1; o >= 1; o >>= 1) {
+    for (int o = top >> 1; o >= 1; o >>= 1) {
         Best c;
-        c.idx = __shfl_xor(b.idx, o, width);
-        c.id = __shfl_xor(b.id, o, width);
-        c.d2 = __shfl_xor(b.d2, o, width);
-        c.rule = __shfl_xor(b.rule, o, width);
-        if (c.idx != kNone && (b.idx == kNone || c.d2 < b.d2 || (c.d2 == b.d2 && c.id < b.id)))
+        c.idx = __shfl_xor(b.idx, o, 64);
+        c.id = __shfl_xor(b.id, o, 64);
+        c.d2 = __shfl_xor(b.d2, o, 64);
+        c.rule = __shfl_xor(b.rule, o, 64);
+        if (o < w && c.idx != kNone &&
+            (b.idx == kNone || c.d2 < b.d2 || (c.d2 == b.d2 && c.id < b.id)))
             b = c;
     }
 }
 
-// O7 search for one claimer j (record rj) by its subgroup of `width` lanes
-// (lane li scans stencil cells li and li + width), then lane 0's Bernoulli
-// draw and handshake keys.
+// O7 search for one claimer j (record rj, id ida) by its group of `width`
+// lanes (lane li scans stencil cells li and li + width; `top` is the widest
+// group of the workgroup), then lane 0's Bernoulli draw and handshake keys.
+// `moved`: steps since the agents were binned.  `wide`: the claimer
+// searches the 27-cell stencil (always where the grid does not allow the
+// 8-cell one; in a step that keeps a binning, also when its species'
+// contact radius plus its targets' moves since the binning exceed the
+// 8-cell stencil's reach of half a cell, less 1 %, as move decided when it
+// flagged the claimer).  Groups are at least half as wide as the stencil.
 template <bool B>
 __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, const PairLds& P,
                                                const Agents& A, uint32_t t, uint32_t j,
-                                               const uint4& rj, int li, int width, int ncell,
-                                               float stale, uint32_t* plocal, uint32_t* nprop)
+                                               const uint4& rj, uint32_t ida, int li, int width,
+                                               int top, bool wide, uint32_t moved,
+                                               uint32_t* plocal, uint32_t* nprop)
 {
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
     const uint32_t s = rj.w & 0xFFu;
+    wide = wide || !T.stencil8;
+    const int ncell = wide ? 27 : 8;
+    const float stale = float(moved) * P.dmax[s];
     const float r2max = P.r2max[s];
     const float x = __uint_as_float(rj.x), y = __uint_as_float(rj.y), z = __uint_as_float(rj.z);
     const int comp = compartment(T, x, y, z);
@@ -832,7 +867,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
     // any candidate listed in the cell; the cell is skipped when that bound
     // exceeds the claimer's largest contact radius, padded by 0.1 % and
     // 1e-3 cells (far above the rounding of the cell coordinates).
-    const float moved = stale * T.inv_h;
+    const float shrink = stale * T.inv_h;
     const float rho = P.rmax[s] * T.inv_h * 1.001f + 1e-3f;
     const float rho2 = rho * rho;
     // candidate range of stencil cell m (empty outside the grid or out of reach)
@@ -843,14 +878,14 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         float gap2 = 0.0f;
         for (int a = 0; a < 3; ++a) {
             int o;
-            if (T.stencil8) {
+            if (!wide) {
                 // the neighbour on the side of the cell the point is nearer
                 o = ((m >> a) & 1) * (f[a] < 0.5f ? -1 : 1);
             } else {
                 o = (a == 0 ? m % 3 : (a == 1 ? (m / 3) % 3 : m / 9)) - 1;
             }
             float g = o < 0 ? f[a] : (o > 0 ? 1.0f - f[a] : 0.0f);
-            g = fmaxf(g - moved, 0.0f);
+            g = fmaxf(g - shrink, 0.0f);
             gap2 += g * g;
             int v = c[a] + o;
             if (periodic) v = (v + G) % G;
@@ -883,11 +918,10 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         k0 += 2;
         k1 += 2;
     }
-    reduce_best(b, width);
+    reduce_best(b, width, top);
     if (li == 0) {
         uint32_t out = kNone;
         if (b.idx != kNone) {
-            const uint32_t ida = A.id[j];
             const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
             if (uint64_t(w) < T.rule[b.rule].thr) {
                 const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
@@ -905,7 +939,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 
 template <bool B>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
-k_propose(Dev d, int p, uint32_t split, int bin, float stale)
+k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint32_t plocal[kPChunk];
@@ -939,6 +973,7 @@ k_propose(Dev d, int p, uint32_t split, int bin, float stale)
         for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kBlock) {
             P.r2max[q] = T.claim_r2max[q];
             P.rmax[q] = T.claim_rmax[q];
+            P.dmax[q] = T.claim_dmax[q];
         }
         if (threadIdx.x == 0) {
             nprop = 0;
@@ -948,25 +983,43 @@ k_propose(Dev d, int p, uint32_t split, int bin, float stale)
     __syncthreads();
     const uint32_t last = first + kPChunk < n ? first + kPChunk : n;
     const Agents A = d.a[p ^ 1];
-    const uint32_t nl = compact_claimers(word, first, last, list, &count);
-    // a subgroup of `width` lanes per claimer, at most two stencil cells
-    // per lane (the stencil is the same for every simulation of a batch)
-    // (never fewer lanes than cover the stencil with two cells each)
-    const int wmin = T.stencil8 ? 4 : 16;
-    const int width = int(d.prop_lanes) > wmin ? int(d.prop_lanes) : wmin;
-    const int ncell = T.stencil8 ? 8 : 27;
-    const int sub = int(threadIdx.x) / width, li = int(threadIdx.x) % width;
-    const int nsub = kBlock / width;
-    for (uint32_t q = uint32_t(sub) + share * uint32_t(nsub); q < nl; q += uint32_t(nsub) * split) {
+    __shared__ uint32_t n_wide;
+    const uint32_t nl = compact_claimers(word, first, last, list, &count, &n_wide);
+    const uint32_t nw = n_wide;
+    // A group of lanes per claimer: `narrow` lanes (4 for the 8-cell
+    // stencil, 16 for the 27-cell one, or the configured count if more)
+    // and `wide` = max(16, narrow) for the claimers that search 27 cells
+    // while the others search 8.  Groups are laid out wide claimers first
+    // over the workgroup's lanes, pass after pass, so every group is
+    // aligned to its width; `split` workgroups sharing a chunk take every
+    // split-th pass.
+    const uint32_t wmin = T.stencil8 ? 4u : 16u;
+    const uint32_t narrow = d.prop_lanes > wmin ? d.prop_lanes : wmin;
+    const uint32_t wide = narrow > 16u ? narrow : 16u;
+    const uint32_t lanes = nw * wide + (nl - nw) * narrow;
+    for (uint32_t v = share * kBlock + threadIdx.x; v - threadIdx.x < lanes; v += kBlock * split) {
+        if (v >= lanes) continue;
+        uint32_t q, width;
+        const bool is_wide = v < nw * wide;
+        if (is_wide) {
+            q = v / wide;
+            width = wide;
+        } else {
+            q = nw + (v - nw * wide) / narrow;
+            width = narrow;
+        }
+        const int li = int(v & (width - 1u));
         const uint32_t j = list[q];
         const uint4 rj = A.rec[j];
+        const uint32_t ida = A.id[j];
         if (B)
             per_sim(sim_of(rj.w), [&](uint32_t u) {
-                search_claimer<true>(d, d.tab[u], P, A, t, j, rj, li, width, ncell, stale, plocal,
-                                     &nprop);
+                search_claimer<true>(d, d.tab[u], P, A, t, j, rj, ida, li, int(width), int(wide),
+                                     is_wide, moved, plocal, &nprop);
             });
         else
-            search_claimer<false>(d, T, P, A, t, j, rj, li, width, ncell, stale, plocal, &nprop);
+            search_claimer<false>(d, T, P, A, t, j, rj, ida, li, int(width), int(wide), is_wide,
+                                  moved, plocal, &nprop);
     }
     // the workgroup's proposers join the step's proposer list (one global
     // atomic per workgroup that has any)
@@ -1111,10 +1164,12 @@ static inline void go(K kernel, unsigned grid, unsigned block, hipStream_t s, co
 
 // the batch variants of the agent kernels (template argument true) resolve
 // each agent's simulation; a single simulation takes the plain ones
-void launch_move(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
+void launch_move(const Dev& d, int p, int record, int bin, uint32_t moved, hipStream_t s,
+                 const KEvents& ev)
 {
-    if (d.n_sims > 1) go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
-    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin);
+    if (d.n_sims > 1)
+        go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin, moved);
+    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin, moved);
 }
 
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
@@ -1127,15 +1182,15 @@ void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvent
     if (d.n_sims > 1) go(k_scatter<true>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
     else go(k_scatter<false>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
 }
-void launch_propose(const Dev& d, int p, int bin, float stale, hipStream_t s, const KEvents& ev)
+void launch_propose(const Dev& d, int p, int bin, uint32_t moved, hipStream_t s, const KEvents& ev)
 {
     // enough workgroups to fill the chip: chunks shared by up to 16
     const unsigned chunks = chunks_for(d.capacity);
     unsigned split = 1;
     const unsigned min_blocks = d.prop_min_blocks ? d.prop_min_blocks : kPropMinBlocks;
     while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
-    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin, stale);
-    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin, stale);
+    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin, moved);
+    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin, moved);
 }
 void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {

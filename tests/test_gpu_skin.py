@@ -30,22 +30,49 @@ def _gpu():
 
 
 def expected_bin_every(m, G, cap=8):
-    """The bound restated: a step moves an agent at most 5.78 sigma along
-    an axis; the 27-cell stencil reaches a cell, the 8-cell one half a
-    cell, less 1 %."""
+    """The bound restated.  A step moves an agent at most 5.78 sigma along
+    an axis, sigma of its species at the time; a claimer species' targets
+    move at most dmax per step, the largest such bound over every species
+    that is or can turn into a target of its rules.  Its reach after j kept
+    steps, largest contact radius + j dmax, must stay within the 27-cell
+    stencil's (a cell, less 1 %); where the grid allows the 8-cell stencil
+    (half a cell), the binning is kept only while the claimer species that
+    would need 27 cells hold at most an eighth of the initial claimers."""
     bim = [r for r in m.rules if r.kind == W.BIMOL]
     if not bim or any(r.kind == W.UNIMOL and r.placement != W.KEEP for r in m.rules):
         return 1
     f32 = np.float32
-    rmax = max(float(f32(r.radius_um)) for r in bim)
-    sigma = max(float(f32(math.sqrt(2.0 * float(f32(s.diffusion_um2_s)) * float(f32(m.dt_s)))))
-                for s in m.species)
+    ns = len(m.species)
+    sigma = [float(f32(math.sqrt(2.0 * float(f32(s.diffusion_um2_s)) * float(f32(m.dt_s)))))
+             for s in m.species]
+    becomes = np.eye(ns, dtype=bool)
+    for r in m.rules:
+        if r.products[0] >= 0:
+            becomes[r.reactants[0], r.products[0]] = True
+        if r.kind == W.BIMOL and r.products[1] >= 0:
+            becomes[r.reactants[1], r.products[1]] = True
+    for k in range(ns):
+        becomes |= becomes[:, [k]] & becomes[[k], :]
+    rmax, dmax = {}, {}
+    for r in bim:
+        a, t = r.reactants
+        rmax[a] = max(rmax.get(a, 0.0), float(f32(r.radius_um)))
+        d = max(float(f32(5.78 * sigma[k])) for k in range(ns) if becomes[k, t])
+        dmax[a] = max(dmax.get(a, 0.0), d)
     ext = float(f32(m.box_um)) if m.geometry == W.PERIODIC_BOX else float(f32(f32(m.outer_radius_um) * f32(2)))
     h = float(f32(ext / G))
-    reach = (0.5 if ext / G >= 2.02 * rmax else 1.0) * h * 0.99
-    if sigma == 0:
-        return cap
-    return min(cap, 1 + max(0, math.floor((reach - rmax) / (5.78 * sigma))))
+    stencil8 = ext / G >= 2.02 * max(rmax.values())
+    k = cap
+    for a in rmax:
+        if dmax[a] > 0:
+            k = min(k, 1 + max(0, math.floor((0.99 * h - rmax[a]) / dmax[a])))
+    if stencil8:
+        while k > 1:
+            wide = sum(m.species[a].count for a in rmax if rmax[a] + (k - 1) * dmax[a] > 0.495 * h)
+            if 8 * wide <= sum(m.species[a].count for a in rmax):
+                break
+            k -= 1
+    return k
 
 
 def slow_c2(n, seed):
@@ -73,10 +100,14 @@ def holes_c2(n, seed):
     return m
 
 
+# cells of 40 nm to 150 nm: 2 to 8 steps per binning; at 61 nm and 100 nm
+# the kinase-1 claimers (whose inhibitor targets are fast) search 27 cells in
+# the later kept steps, everyone else 8
 CASES = [
-    ("c2_8cell_k2", lambda: W.c2(50_000, seed=31, steps=60), 0.06),
-    ("c2_8cell_k3", lambda: W.c2(50_000, seed=32, steps=60), 0.10),
-    ("c2_8cell_k4", lambda: W.c2(50_000, seed=33, steps=60), 0.15),
+    ("c2_cell40nm", lambda: W.c2(50_000, seed=30, steps=60), 0.04),
+    ("c2_cell61nm", lambda: W.c2(50_000, seed=31, steps=60), 0.06),
+    ("c2_cell100nm", lambda: W.c2(50_000, seed=32, steps=60), 0.10),
+    ("c2_cell150nm", lambda: W.c2(50_000, seed=33, steps=60), 0.15),
     ("c2_27cell", lambda: slow_c2(40_000, 34), 0.019),
     ("box", lambda: box_no_births(6000, 35), 0.06),
     ("holes", lambda: holes_c2(40_000, 36), 0.10),
@@ -176,17 +207,12 @@ def test_ring_over_kept_steps():
     assert np.array_equal(counts[:, 0, :], np.array(want))
 
 
-def test_default_grid_is_coarsened_to_keep_binning():
-    # 95k agents at the cascade's density: the power-of-two grid (64 per
-    # axis) has cells just too small to keep the cell lists for a step; the
-    # default takes the 63-cell grid instead, and the results stay exact
+def test_cascade_default_grid_keeps_binning_four_steps():
+    # the 2M-agent cascade on its default 128^3 grid: the kinase-1 claimers
+    # need 27 cells from the second kept step on, so a binning lasts 4 steps
     import paper_2606_14603_amd as mabm
-    m = W.c2(95_000, seed=40, steps=60)
-    g = mabm.Sim(m, record=True)
+    m = W.c2(2_000_000)
+    g = mabm.Sim(m)
     G, _ = g.grid()
-    assert G == 63
-    assert g.get_param(mabm.PARAM_BIN_EVERY) == expected_bin_every(m, G) == 2
-    o = oracle.OracleSim(m, grid_n=G)
-    g.step(9)
-    o.step(9)
-    assert_same(g.export(), o.export(), "coarsened default grid")
+    assert G == 128
+    assert g.get_param(mabm.PARAM_BIN_EVERY) == expected_bin_every(m, G) == 4
