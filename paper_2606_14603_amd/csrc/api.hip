@@ -123,7 +123,7 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.tile_acc = take((size_t)2 * L.ntiles * kTileStride * 4);
     L.slot = take(cap * 8);
     L.prop = take(cap * 4);
-    L.plist = take(cap * 4);
+    L.plist = take(cap * 16);
     L.rkey = take(cap * 4);
     L.revent = take(cap);
     L.rpartner = take(cap * 4);
@@ -509,7 +509,7 @@ void fill_dev(mabm_sim* s)
     d.tile_acc = (uint32_t*)(A + L.tile_acc);
     d.slot = (unsigned long long*)(A + L.slot);
     d.prop = (uint32_t*)(A + L.prop);
-    d.plist = (uint32_t*)(A + L.plist);
+    d.plist = (uint4*)(A + L.plist);
     d.rkey = (uint32_t*)(A + L.rkey);
     d.revent = A + L.revent;
     d.rpartner = (uint32_t*)(A + L.rpartner);

@@ -24,7 +24,6 @@ constexpr uint32_t kMetaSimShift = 16;
 constexpr uint32_t kMetaSimMask = 0xFFFF0000u;
 constexpr uint32_t kMaxSims = 65535;
 constexpr int kMetaSpeciesByte = 12;        // byte offset of the species in a record
-constexpr int kMetaFlagsByte = 13;          // byte offset of the flags in a record
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
 constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
@@ -138,7 +137,7 @@ struct Dev {
                            // accumulated by move, one set per parity
     unsigned long long* slot;
     uint32_t* prop;        // per sorted agent: proposed partner index
-    uint32_t* plist;       // sorted indices of this step's proposing claimers
+    uint4* plist;          // this step's proposals {claimer, target, their ids}
     uint32_t* rkey;        // record arrays, indexed like the current agents
     uint8_t* revent;
     uint32_t* rpartner;

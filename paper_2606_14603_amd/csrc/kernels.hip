@@ -124,10 +124,6 @@ __device__ __forceinline__ void set_species(const Agents& A, uint32_t j, uint32_
     reinterpret_cast<uint8_t*>(A.rec + j)[kMetaSpeciesByte] = uint8_t(s);
 }
 
-__device__ __forceinline__ uint32_t flags_of(const Agents& A, uint32_t j)
-{
-    return uint32_t(reinterpret_cast<const uint8_t*>(A.rec + j)[kMetaFlagsByte]) << 8;
-}
 
 // ---------------------------------------------------------------------------
 // O0: initial placement.  Agent i (id i) belongs to the first species whose
@@ -371,9 +367,9 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int b
     // claim slots start every step at all-ones: the previous step wrote only
     // those of its proposers and their targets, which are reset here
     if (i < d.ctl->n_prop[p ^ 1]) {
-        const uint32_t j = d.plist[i];
-        d.slot[j] = ~0ull;
-        d.slot[d.prop[j]] = ~0ull;
+        const uint4 e = d.plist[i];
+        d.slot[e.x] = ~0ull;
+        d.slot[e.y] = ~0ull;
     }
     uint32_t key = kNone;
     uint4 r = {0u, 0u, 0u, kDead};
@@ -699,6 +695,7 @@ __device__ void kept_bookkeeping(const Dev& d, int p)
 // other set-up loads.  Returns the list length, and the wide claimers'
 // count in *n_wide.
 constexpr int kClaimPer = kPChunk / kBlock;
+constexpr uint32_t kPropLds = 256;  // proposals a workgroup stages in LDS
 static_assert(kClaimPer == 2 || kClaimPer == 4, "two or four claimer flags per thread");
 using FlagWord = std::conditional_t<kClaimPer == 4, uint32_t, uint16_t>;
 
@@ -842,7 +839,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
                                                const Agents& A, uint32_t t, uint32_t j,
                                                const uint4& rj, uint32_t ida, int li, int width,
                                                int top, bool wide, uint32_t moved,
-                                               uint32_t* plocal, uint32_t* nprop)
+                                               uint4* plocal, uint32_t* nprop, uint32_t* n_prop)
 {
     const int G = int(T.G);
     const bool periodic = T.geometry == kBox;
@@ -930,7 +927,13 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
                 atomicMin(&d.slot[j], pr | b.id);
                 atomicMin(&d.slot[b.idx], pr | ida);
                 out = b.idx;
-                plocal[atomicAdd(nprop, 1u)] = j;
+                // the proposal, staged in LDS for the workgroup's one
+                // reservation in the step's list (the rare overflow
+                // reserves its own entry)
+                const uint4 e{j, b.idx, ida, b.id};
+                const uint32_t k = atomicAdd(nprop, 1u);
+                if (k < kPropLds) plocal[k] = e;
+                else d.plist[atomicAdd(n_prop, 1u)] = e;
             }
         }
         d.prop[j] = out;
@@ -942,7 +945,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))
 k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
 {
     __shared__ uint32_t list[kPChunk];
-    __shared__ uint32_t plocal[kPChunk];
+    __shared__ uint4 plocal[kPropLds];
     __shared__ PairLds P;
     __shared__ uint32_t count, nprop, pbase;
     const Tables& T = *d.tab;
@@ -1015,16 +1018,16 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
         if (B)
             per_sim(sim_of(rj.w), [&](uint32_t u) {
                 search_claimer<true>(d, d.tab[u], P, A, t, j, rj, ida, li, int(width), int(wide),
-                                     is_wide, moved, plocal, &nprop);
+                                     is_wide, moved, plocal, &nprop, &d.ctl->n_prop[p]);
             });
         else
             search_claimer<false>(d, T, P, A, t, j, rj, ida, li, int(width), int(wide), is_wide,
-                                  moved, plocal, &nprop);
+                                  moved, plocal, &nprop, &d.ctl->n_prop[p]);
     }
     // the workgroup's proposers join the step's proposer list (one global
     // atomic per workgroup that has any)
     __syncthreads();
-    const uint32_t np = nprop;
+    const uint32_t np = nprop < kPropLds ? nprop : kPropLds;
     if (np == 0) return;
     if (threadIdx.x == 0) pbase = atomicAdd(&d.ctl->n_prop[p], np);
     __syncthreads();
@@ -1051,19 +1054,22 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     __syncthreads();
     const Agents A = d.a[p ^ 1];
     for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < np; q += gridDim.x * kBlock) {
-        const uint32_t j = d.plist[q];
-        const uint32_t b = d.prop[j];
-        const uint32_t ida = A.id[j], idb = A.id[b];
+        const uint4 e = d.plist[q];
+        const uint32_t j = e.x, b = e.y, ida = e.z, idb = e.w;
+        // everything the confirmation and the products need, requested
+        // together (no other thread writes the species of a confirmed
+        // pair, and the flag byte is never rewritten)
+        const uint32_t wj = A.rec[j].w, wb = A.rec[b].w, pb = d.prop[b];
+        const unsigned long long slot_j = d.slot[j], slot_b = d.slot[b];
         const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
         // the pair's simulation gives the Philox key
-        const Tables& Tk = B ? d.tab[sim_of(A.rec[j].w)] : T;
+        const Tables& Tk = B ? d.tab[sim_of(wj)] : T;
         const unsigned long long pr = (unsigned long long)draw(Tk, lo_id, t, kPrio, hi_id).w0 << 32;
-        if (d.slot[j] != (pr | idb) || d.slot[b] != (pr | ida)) continue;
+        if (slot_j != (pr | idb) || slot_b != (pr | ida)) continue;
         // b proposed too only if it carries the claimer flag (its prop is
-        // then this step's); a mutual pair fires once, from the lower id.
-        // Species are read only once this thread owns the pair.
-        if (idb < ida && (flags_of(A, b) & kMetaClaimer) && d.prop[b] == j) continue;
-        const uint32_t sj = A.rec[j].w & 0xFFu, sb = A.rec[b].w & 0xFFu;
+        // then this step's); a mutual pair fires once, from the lower id
+        if (idb < ida && (wb & kMetaClaimer) && pb == j) continue;
+        const uint32_t sj = wj & 0xFFu, sb = wb & 0xFFu;
         const RuleDev& R = T.rule[T.rule_of[sj][sb]];
         set_species(A, j, R.p0 < 0 ? kDead : uint32_t(R.p0));
         set_species(A, b, R.p1 < 0 ? kDead : uint32_t(R.p1));
