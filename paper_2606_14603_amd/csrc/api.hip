@@ -382,6 +382,21 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
     // spatial hash: G cells per axis, cell size >= 1.01 R_max
     const double ext = extent_of(c);
     uint32_t G = grid_from_config(c);
+    // Default grid: the power of two nearest (in log) to cells holding two
+    // of the initial agents on average over the volume they fill, if that is
+    // coarser than the arena's grid (sized from the capacity, which counts
+    // room for births, over the whole bounding box).  A search costs little
+    // more at a few agents per cell while the cell tables, which the
+    // counting sort scans at every binning, shrink with the cube of the cell.
+    if (c.cell_um <= 0.0f && acc > 0) {
+        const double pi = 3.14159265358979323846;
+        const double vol = c.geometry == MABM_PERIODIC_BOX
+                               ? ext * ext * ext
+                               : 4.0 / 3.0 * pi * std::pow((double)c.outer_radius_um, 3.0);
+        const double h = std::cbrt(2.0 * vol / (double)acc);
+        const double g = std::exp2(std::round(std::log2(ext / h)));
+        G = std::min(G, (uint32_t)std::min((double)kMaxGrid, std::max(3.0, g)));
+    }
     if (rmax > 0.0 && ext / G < 1.01 * rmax) {
         if (c.cell_um > 0.0f)
             return fail(s, MABM_E_INVALID, "cell_um smaller than 1.01 x the largest contact radius");
@@ -530,9 +545,16 @@ mabm_status finalize(mabm_sim* s, bool place)
     Dev& d = s->dev;
     const Tables& last = s->tabs.back();
     d.ncells = last.cell_base + (1u << (3 * last.morton_bits));
-    d.tile_shift = s->lay.tile_shift;
-    d.ntiles = (uint32_t)(((size_t)d.ncells + ((size_t)kScanTile << d.tile_shift) - 1) >>
-                          (kScanTileLog + d.tile_shift));
+    // the fewest passes per scan tile that keep the tiles within the
+    // arena's tile sums (the grid may be coarser than the one the arena
+    // was sized for; fewer, longer tiles would put more of move's tile-sum
+    // atomics on each counter)
+    auto tiles = [&](uint32_t sh) {
+        return ((size_t)d.ncells + ((size_t)kScanTile << sh) - 1) >> (kScanTileLog + sh);
+    };
+    d.tile_shift = 0;
+    while (tiles(d.tile_shift) > s->lay.ntiles) ++d.tile_shift;
+    d.ntiles = (uint32_t)tiles(d.tile_shift);
     // agents placed: every simulation's initial counts, one after another
     std::vector<uint32_t> n_init(s->n_sims);
     uint32_t total = 0;
