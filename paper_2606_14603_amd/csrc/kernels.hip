@@ -591,6 +591,10 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
             if (rs + 1u == ns) d.next_id[sim] += ns;
         }
     }
+    // the scan has read this parity's tile sums (and cleared the other's):
+    // clear them too, so that steps keeping this binning need not
+    uint32_t* acc = tile_acc(d, p);
+    for (uint32_t k = threadIdx.x; k < d.ntiles; k += kBlock) acc[size_t(k) * kTileStride] = 0u;
     if (threadIdx.x == 0) {
         if (err) atomicOr(&ctl->err, err);
         // live agents at this step's start: its slots minus the holes in
@@ -656,31 +660,27 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
 
 // ---------------------------------------------------------------------------
 // bookkeeping of a step that keeps the previous step's cell lists (there is
-// no scan or scatter; run by the first workgroup of finish, after the
-// search): nothing was binned or compacted, holes are carried to the next
-// step, and the scan's clearing of the other parity's tile sums is done
-// here.
+// no scan or scatter; run by one thread of finish, after the search):
+// nothing was binned or compacted, and holes are carried to the next step
+// (both parities' tile sums are already clear: the binning's scatter
+// cleared the ones its scan had read).
 // ---------------------------------------------------------------------------
 __device__ void kept_bookkeeping(const Dev& d, int p)
 {
     Ctl* ctl = d.ctl;
-    uint32_t* acc = tile_acc(d, p ^ 1);
-    for (uint32_t k = threadIdx.x; k < d.ntiles; k += kBlock) acc[size_t(k) * kTileStride] = 0u;
-    if (threadIdx.x == 0) {
-        const StepState cur = ctl->s[p];
-        const uint32_t prev_holes = ctl->holes[p ^ 1];
-        ctl->n_binned = cur.n_slots;
-        ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
-        ctl->dead_base += prev_holes + ctl->uni_dead[p];
-        ctl->uni_dead[p] = 0u;
-        ctl->holes[p ^ 1] = 0u;
-        ctl->n_births[p ^ 1] = 0u;
-        ctl->n_prop[p ^ 1] = 0u;
-        // such a step has no births (the library keeps the binning only for
-        // models without birth or translocation rules)
-        if (ctl->n_births[p]) atomicOr(&ctl->err, kErrKeptBinning);
-        ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots, cur.next_id, 0u};
-    }
+    const StepState cur = ctl->s[p];
+    const uint32_t prev_holes = ctl->holes[p ^ 1];
+    ctl->n_binned = cur.n_slots;
+    ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
+    ctl->dead_base += prev_holes + ctl->uni_dead[p];
+    ctl->uni_dead[p] = 0u;
+    ctl->holes[p ^ 1] = 0u;
+    ctl->n_births[p ^ 1] = 0u;
+    ctl->n_prop[p ^ 1] = 0u;
+    // such a step has no births (the library keeps the binning only for
+    // models without birth or translocation rules)
+    if (ctl->n_births[p]) atomicOr(&ctl->err, kErrKeptBinning);
+    ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots, cur.next_id, 0u};
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
@@ -1046,7 +1046,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     __shared__ uint32_t s_holes;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
-    if (!bin && blockIdx.x == 0) kept_bookkeeping(d, p);
+    if (!bin && blockIdx.x == 0 && threadIdx.x == 0) kept_bookkeeping(d, p);
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
     if (blockIdx.x * kBlock >= np) return;
