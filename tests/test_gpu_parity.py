@@ -192,3 +192,25 @@ def test_graph_replay_matches_direct_launches():
             assert np.array_equal(g.counts()[0], e.counts()[0])
             assert g.agent_updates() == e.agent_updates()
         say(f"[graphs] {m.name} ok at t={done}")
+
+
+def test_dense_box_overflows_the_workgroup_proposal_stage():
+    # 8,000 agents in a 0.2 um box with binding certain on contact: in the
+    # first step 2,259 of the 4,000 claimers bind.  With one workgroup per
+    # chunk of 1,024 agents, most of a chunk's ~500 claimers propose, more
+    # than the 256 proposals a workgroup stages in LDS, so the rest reserve
+    # their list entries one by one; results stay the oracle's
+    import paper_2606_14603_amd as mabm
+    m = W.c1(n_a=4000, n_b=4000, box_um=0.2, bind_p=1.0, unbind_p=0.02)
+    m.seed = 77
+    g = mabm.Sim(m, record=True)
+    g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, 1)
+    G, _ = g.grid()
+    o = oracle.OracleSim(m, grid_n=G)
+    done = 0
+    for c in (1, 2, 5, 12):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        assert_same(g.export(), o.export(), f"dense box t={c}")
+    assert o.counts()[0][2] > 2000
