@@ -80,7 +80,7 @@ bool config_ok(const mabm_config* c, std::string& why)
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
     size_t ctl, tab, rec[2], id[2], rank, event, sclaim, cell_count, cell_start, tile_acc, slot,
-        prop, plist, rkey, revent, rpartner, births, counts, next_id, total;
+        prop, plist, rkey, revent, rpartner, births, counts, next_id, head, nxt, glob, total;
     uint32_t ncells, ntiles, tile_shift;
 };
 
@@ -130,6 +130,9 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.births = take((size_t)kMaxBirthsPerStep * sizeof(Birth));
     L.counts = take((size_t)kMaxSpecies * 8 * n);
     L.next_id = take((size_t)4 * n);
+    L.head = take((padded + 1) * 4);
+    L.nxt = take(cap * 4);
+    L.glob = take(cap * 4);
     L.total = off;
     return L;
 }
@@ -268,22 +271,29 @@ void timed(mabm_sim* s, int kid, F&& launch)
 // for the 8-cell stencil, a whole cell for the 27-cell one, less 1 %),
 // every partner within reach is still found and the results are those of
 // binning every step; a claimer species whose reach outgrows the 8-cell
-// stencil searches 27 cells in the later kept steps.  Births and
-// translocations put agents far from any cell list, so models with such
-// rules, and models without pair rules, bin every step.
+// stencil searches 27 cells in the later kept steps.  Agents that rules
+// place (newborns, translocated agents, split parents) are far from any
+// cell list: while a binning is kept they join extra per-cell chains at
+// their new positions (or, placed twice, a global list), which the search
+// reads too.  Models without pair rules bin every step (nothing searches).
 constexpr uint32_t kMaxBinEvery = 8;
 constexpr double kNormalBound = 5.78;
 
 // whether the model allows keeping cell lists at all: it has pair rules
-// (else nothing searches them) and no births or translocations
+// (else nothing searches them)
 bool may_keep_binning(const mabm_sim* s)
 {
-    bool bimol = false;
-    for (const mabm_rule& u : s->rules) {
-        if (u.kind == MABM_UNIMOL && u.placement != MABM_KEEP) return false;
-        if (u.kind == MABM_BIMOL) bimol = true;
-    }
-    return bimol;
+    for (const mabm_rule& u : s->rules)
+        if (u.kind == MABM_BIMOL) return true;
+    return false;
+}
+
+// whether the model has rules that place agents (births, translocations)
+bool places_agents(const mabm_sim* s)
+{
+    for (const mabm_rule& u : s->rules)
+        if (u.kind == MABM_UNIMOL && u.placement != MABM_KEEP) return true;
+    return false;
 }
 
 // tables of simulation k of s (the only one, or one of a batch)
@@ -486,6 +496,7 @@ void set_schedule(mabm_sim* s)
     }
     s->bin_every = std::max(1u, k);
     s->kept = s->bin_every - 1;  // the next step bins
+    s->dev.link = s->bin_every > 1 && places_agents(s) ? 1u : 0u;
 }
 
 // whether the next step bins, given the steps kept since the last binning
@@ -531,6 +542,9 @@ void fill_dev(mabm_sim* s)
     d.births = (Birth*)(A + L.births);
     d.counts = (unsigned long long*)(A + L.counts);
     d.next_id = (uint32_t*)(A + L.next_id);
+    d.head = (uint32_t*)(A + L.head);
+    d.nxt = (uint32_t*)(A + L.nxt);
+    d.glob = (uint32_t*)(A + L.glob);
     d.capacity = (uint32_t)total_capacity(s->cfgs.data(), s->n_sims);
     d.n_sims = s->n_sims;
 }
@@ -602,8 +616,6 @@ mabm_status sync_ctl(mabm_sim* s, Ctl* out)
         s->failed = true;
         if (out->err & kErrPlacement) return fail(s, MABM_E_DEVICE, "initial placement failed after 64 attempts");
         if (out->err & kErrBirths) return fail(s, MABM_E_CAPACITY, "more than 4096 births in one step");
-        if (out->err & kErrKeptBinning)
-            return fail(s, MABM_E_DEVICE, "births in a step that kept the previous binning");
         return fail(s, MABM_E_CAPACITY, "agent capacity exceeded by births");
     }
     return MABM_OK;

@@ -25,6 +25,15 @@ constexpr uint32_t kMetaSimMask = 0xFFFF0000u;
 constexpr uint32_t kMaxSims = 65535;
 constexpr int kMetaSpeciesByte = 12;        // byte offset of the species in a record
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Extra cell lists of a kept binning: agents placed since the binning
+// (newborns, translocated agents, split parents) are chained per cell
+// through `nxt`; kEnd ends a chain, kUnlinked marks a slot in no chain, and
+// kGlobBit a chained slot placed again, which then sits in the global list
+// every claimer reads.
+constexpr uint32_t kEnd = 0x7FFFFFFFu;
+constexpr uint32_t kUnlinked = 0x7FFFFFFEu;
+constexpr uint32_t kGlobBit = 0x80000000u;
+constexpr uint32_t kMaxSlots = 0x7FFFFFF0u;  // slot indices stay below kUnlinked
 constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
 constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
 constexpr int kScanItems = 8;                 // cells per thread in the scan
@@ -48,7 +57,7 @@ enum Geometry : int32_t { kBox = 0, kSphere = 1, kNested = 2 };
 enum Placement : int32_t { kKeep = 0, kSplit = 1, kEmit = 2, kTranslocate = 3 };
 
 // sticky device error bits
-enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u, kErrKeptBinning = 8u };
+enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u };
 
 struct RuleDev {
     int32_t kind, placement, p0, p1, to;
@@ -105,11 +114,11 @@ struct Ctl {
     uint32_t n_births[2];  // birth records appended by the step of parity p
     uint32_t holes[2];     // agents consumed by pair rules in the step of parity p
     uint32_t n_prop[2];    // entries of the proposer list of the step of parity p
-    uint32_t n_binned;     // agents binned in the current step (all slots in a step
-                           // that keeps the previous binning)
+    uint32_t n_binned;     // agents binned by the last binning (births follow them)
     uint32_t uni_dead[2];  // agents removed by unimolecular rules in the step of parity p
     uint32_t dead_base;    // holes at the step's start older than the previous step's
                            // pair rules (steps that keep the binning compact nothing)
+    uint32_t n_glob;       // entries of the global list of agents placed again
     uint32_t err;          // ErrBit, sticky
     unsigned long long agent_updates;  // sum of live agents at step starts
 };
@@ -144,6 +153,10 @@ struct Dev {
     Birth* births;
     unsigned long long* counts;  // [n_sims][kMaxSpecies]
     uint32_t* next_id;           // batch: per simulation, the next id to assign
+    uint32_t* head;              // per cell: first agent of its extra chain (kEnd: none)
+    uint32_t* nxt;               // per slot: next agent of its chain, kUnlinked, kGlobBit
+    uint32_t* glob;              // agents placed twice since the binning
+    uint32_t link;               // keep extra chains (kept binnings with placements)
     uint32_t capacity, ncells, ntiles, n_init;
     uint32_t tile_shift;         // a scan tile is kScanTile << tile_shift cells
     uint32_t n_sims;             // 1: a single simulation; tab has n_sims entries

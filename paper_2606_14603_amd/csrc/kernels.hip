@@ -171,6 +171,14 @@ __global__ void __launch_bounds__(kBlock) k_fill_records(Dev d)
     d.rkey[i] = kNone;
     d.revent[i] = kNoEvent;
     d.rpartner[i] = kNone;
+    d.nxt[i] = kUnlinked;
+}
+
+// empty extra chains in every (padded) cell
+__global__ void __launch_bounds__(kBlock) k_fill_heads(Dev d, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) d.head[i] = kEnd;
 }
 
 // Release offset of a split or emission (O8): cube rejection in the ball of
@@ -271,7 +279,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
 
     uint32_t fs = s;
     float fx = x1, fy = y1, fz = w1;
-    bool dies = false;
+    bool dies = false, placed = false;  // placed: moved by its rule, not only by diffusion
     if (ev >= 0) {
         const RuleDev& R = T.rule[ev];
         float ux, uy, uz;
@@ -281,6 +289,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
             else fs = uint32_t(R.p0);
             break;
         case kTranslocate: {
+            placed = true;
             const float n2 = sq3(x1, y1, w1);
             if (n2 == 0.0f) {
                 fx = R.target_r;
@@ -296,6 +305,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
             break;
         }
         case kSplit: {
+            placed = true;
             release_offset(T, R, id, t, x1, y1, w1, true, ux, uy, uz);
             fs = uint32_t(R.p0);
             fx = x1 + ux;
@@ -352,6 +362,20 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
             d.rkey[i] = linear_cell(T, cell_of(T, fx, fy, fz));
             d.revent[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
             d.rpartner[i] = kNone;
+        }
+        if (placed && d.link) {
+            // far from its cell list now: it heads the extra chain of its new
+            // cell, or, if already chained since the binning, joins the
+            // global list (each slot at most once in each)
+            uint32_t c = cell_of(T, fx, fy, fz);
+            if (B) c += T.cell_base;
+            const uint32_t old = d.nxt[i];
+            if ((old & ~kGlobBit) == kUnlinked) {
+                d.nxt[i] = atomicExch(&d.head[c], i);
+            } else if (!(old & kGlobBit)) {
+                d.nxt[i] = old | kGlobBit;
+                d.glob[atomicAdd(&d.ctl->n_glob, 1u)] = i;
+            }
         }
     }
     return false;
@@ -455,6 +479,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
                                            threadIdx.x * kScanItems);
     uint4* st4 = reinterpret_cast<uint4*>(d.cell_start + (size_t(tile) << (kScanTileLog + d.tile_shift)) +
                                           threadIdx.x * kScanItems);
+    // the extra chains of the previous binning end with this one
+    uint4* hd4 = reinterpret_cast<uint4*>(d.head + (size_t(tile) << (kScanTileLog + d.tile_shift)) +
+                                          threadIdx.x * kScanItems);
     constexpr uint32_t kPassVec = kScanTile / 4;  // uint4 per pass
     // the first pass's counts are requested before the preceding tiles'
     // sums, so both loads are in flight together
@@ -492,6 +519,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
             run += v[k].w;
             st4[pass * kPassVec + k] = o;
             cnt4[pass * kPassVec + k] = uint4{0u, 0u, 0u, 0u};
+            if (d.link) hd4[pass * kPassVec + k] = uint4{kEnd, kEnd, kEnd, kEnd};
         }
         base += total;
         if (pass + 1 < npass) {
@@ -509,32 +537,31 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 }
 
 // ---------------------------------------------------------------------------
-// births and bookkeeping (O9, O10), run by the extra last workgroup of the
-// scatter launch: child r of the step, ranked by parent id among the step's
+// births (O9): child r of the step, ranked by parent id among the step's
 // births (ranks by counting: parent ids are distinct, as a parent has at most
-// one child per step), goes to slot n_binned + r with id next_id + r; then
-// the next step's scalars.
+// one child per step), goes to slot base + r of A with id next_id + r (in a
+// batch, slots follow (simulation, parent id) and ids are per simulation).
+// A child takes no part in its birth step's search (busy flag).  While a
+// binning is kept, each child also heads the extra chain of its cell.  Run
+// by one whole workgroup; returns the births placed and sets *err (then
+// none is placed).
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRankLds = 1024;  // births ranked from LDS; more read from L2
 
 template <bool B>
-__device__ void births_and_bookkeeping(const Dev& d, int p, int record)
+__device__ uint32_t place_births(const Dev& d, int p, const Agents& A, uint32_t base,
+                                 uint32_t next_id, int record, uint32_t* err)
 {
     __shared__ uint32_t skey[kRankLds], ssim[kRankLds];
-    Ctl* ctl = d.ctl;
-    const StepState cur = ctl->s[p];
-    const uint32_t nbin = ctl->n_binned;
-    uint32_t nb = ctl->n_births[p];
-    uint32_t err = 0;
+    uint32_t nb = d.ctl->n_births[p];
+    *err = 0;
     if (nb > kMaxBirthsPerStep) {
-        err = kErrBirths;
+        *err = kErrBirths;
         nb = 0;
-    } else if (uint64_t(nbin) + nb > d.capacity) {
-        err = kErrCapacity;
+    } else if (uint64_t(base) + nb > d.capacity) {
+        *err = kErrCapacity;
         nb = 0;
     }
-    // a birth's order key: its parent id, and in a batch its simulation
-    // first (slots follow (simulation, parent id); ids are per simulation)
     const bool in_lds = nb <= kRankLds;
     if (in_lds)
         for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
@@ -543,7 +570,6 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
             ssim[k] = bb.sp >> kMetaSimShift;
         }
     __syncthreads();
-    const Agents A = d.a[p ^ 1];
     for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
         const Birth bb = d.births[k];
         const uint32_t sim = bb.sp >> kMetaSimShift;
@@ -565,13 +591,19 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
                 r += pm < bb.parent ? 1u : 0u;
             }
         }
-        const uint32_t j = nbin + r;
-        A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp);
-        A.id[j] = B ? d.next_id[sim] + rs : cur.next_id + r;
+        const uint32_t j = base + r;
+        A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp | kMetaBusy);
+        A.id[j] = B ? d.next_id[sim] + rs : next_id + r;
         if (record) {
             d.rkey[j] = kNone;
             d.revent[j] = kNoEvent;
             d.rpartner[j] = kNone;
+        }
+        if (d.link) {
+            const Tables& T = d.tab[B ? sim : 0u];
+            uint32_t key = cell_of(T, bb.x, bb.y, bb.z);
+            if (B) key += T.cell_base;
+            d.nxt[j] = atomicExch(&d.head[key], j);
         }
     }
     if (B) {
@@ -591,6 +623,20 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
             if (rs + 1u == ns) d.next_id[sim] += ns;
         }
     }
+    return nb;
+}
+
+// Births and bookkeeping of a binning step (O9, O10), run by the extra last
+// workgroup of the scatter launch: births follow the binned agents in the
+// sorted buffer; then the next step's scalars.
+template <bool B>
+__device__ void births_and_bookkeeping(const Dev& d, int p, int record)
+{
+    Ctl* ctl = d.ctl;
+    const StepState cur = ctl->s[p];
+    const uint32_t nbin = ctl->n_binned;
+    uint32_t err;
+    const uint32_t nb = place_births<B>(d, p, d.a[p ^ 1], nbin, cur.next_id, record, &err);
     // the scan has read this parity's tile sums (and cleared the other's):
     // clear them too, so that steps keeping this binning need not
     uint32_t* acc = tile_acc(d, p);
@@ -606,7 +652,34 @@ __device__ void births_and_bookkeeping(const Dev& d, int p, int record)
         ctl->holes[p ^ 1] = 0u;
         ctl->n_births[p ^ 1] = 0u;
         ctl->n_prop[p ^ 1] = 0u;
+        ctl->n_glob = 0u;
         ctl->s[p ^ 1] = StepState{cur.t + 1u, nbin + nb, cur.next_id + nb, 0u};
+    }
+}
+
+// Births and bookkeeping of a step that keeps the previous step's cell
+// lists (there is no scan or scatter; run by the first workgroup of finish,
+// after the search): births follow the step's slots in place, nothing is
+// compacted, and holes are carried to the next step (both parities' tile
+// sums are already clear: the binning's scatter cleared the ones its scan
+// had read).
+template <bool B>
+__device__ void kept_bookkeeping(const Dev& d, int p, int record)
+{
+    Ctl* ctl = d.ctl;
+    const StepState cur = ctl->s[p];
+    uint32_t err;
+    const uint32_t nb = place_births<B>(d, p, d.a[p ^ 1], cur.n_slots, cur.next_id, record, &err);
+    if (threadIdx.x == 0) {
+        if (err) atomicOr(&ctl->err, err);
+        const uint32_t prev_holes = ctl->holes[p ^ 1];
+        ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
+        ctl->dead_base += prev_holes + ctl->uni_dead[p];
+        ctl->uni_dead[p] = 0u;
+        ctl->holes[p ^ 1] = 0u;
+        ctl->n_births[p ^ 1] = 0u;
+        ctl->n_prop[p ^ 1] = 0u;
+        ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots + nb, cur.next_id + nb, 0u};
     }
 }
 
@@ -646,6 +719,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
     O.rec[j] = r;
     O.id[j] = A.id[i];
     d.sclaim[j] = claim ? 1 : 0;
+    if (d.link) d.nxt[j] = kUnlinked;  // binned: in no extra chain
     if (record) {
         if (B) {
             const Tables& Ts = d.tab[sim_of(r.w)];
@@ -656,31 +730,6 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
     }
-}
-
-// ---------------------------------------------------------------------------
-// bookkeeping of a step that keeps the previous step's cell lists (there is
-// no scan or scatter; run by one thread of finish, after the search):
-// nothing was binned or compacted, and holes are carried to the next step
-// (both parities' tile sums are already clear: the binning's scatter
-// cleared the ones its scan had read).
-// ---------------------------------------------------------------------------
-__device__ void kept_bookkeeping(const Dev& d, int p)
-{
-    Ctl* ctl = d.ctl;
-    const StepState cur = ctl->s[p];
-    const uint32_t prev_holes = ctl->holes[p ^ 1];
-    ctl->n_binned = cur.n_slots;
-    ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
-    ctl->dead_base += prev_holes + ctl->uni_dead[p];
-    ctl->uni_dead[p] = 0u;
-    ctl->holes[p ^ 1] = 0u;
-    ctl->n_births[p ^ 1] = 0u;
-    ctl->n_prop[p ^ 1] = 0u;
-    // such a step has no births (the library keeps the binning only for
-    // models without birth or translocation rules)
-    if (ctl->n_births[p]) atomicOr(&ctl->err, kErrKeptBinning);
-    ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots, cur.next_id, 0u};
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
@@ -838,7 +887,7 @@ template <bool B>
 __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, const PairLds& P,
                                                const Agents& A, uint32_t t, uint32_t j,
                                                const uint4& rj, uint32_t ida, int li, int width,
-                                               int top, bool wide, uint32_t moved,
+                                               int top, bool wide, uint32_t moved, uint32_t n_glob,
                                                uint4* plocal, uint32_t* nprop, uint32_t* n_prop)
 {
     const int G = int(T.G);
@@ -867,9 +916,11 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
     const float shrink = stale * T.inv_h;
     const float rho = P.rmax[s] * T.inv_h * 1.001f + 1e-3f;
     const float rho2 = rho * rho;
-    // candidate range of stencil cell m (empty outside the grid or out of reach)
-    auto range = [&](int m, uint32_t& lo, uint32_t& hi) {
+    // candidate range of stencil cell m and the head of its extra chain
+    // (empty outside the grid or out of reach)
+    auto range = [&](int m, uint32_t& lo, uint32_t& hi, uint32_t& hd) {
         lo = hi = 0;
+        hd = kEnd;
         if (m >= ncell) return;
         int cc[3];
         float gap2 = 0.0f;
@@ -894,10 +945,11 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         if (B) cell += T.cell_base;
         lo = d.cell_start[cell];
         hi = d.cell_start[cell + 1];
+        if (d.link) hd = d.head[cell];
     };
-    uint32_t k0, e0, k1, e1;
-    range(li, k0, e0);
-    range(li + width, k1, e1);
+    uint32_t k0, e0, k1, e1, h0, h1;
+    range(li, k0, e0, h0);
+    range(li + width, k1, e1, h1);
     Best b{kNone, 0u, 0.0f, -1};
     // up to two candidates of each cell per round, all four records
     // requested together
@@ -914,6 +966,18 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, r2max, b);
         k0 += 2;
         k1 += 2;
+    }
+    if (d.link) {
+        // agents placed since the binning: the cells' extra chains, and the
+        // global list (agents placed twice), shared among the group's lanes
+        for (uint32_t k = h0; k != kEnd; k = d.nxt[k] & ~kGlobBit)
+            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+        for (uint32_t k = h1; k != kEnd; k = d.nxt[k] & ~kGlobBit)
+            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+        for (uint32_t q = uint32_t(li); q < n_glob; q += uint32_t(width)) {
+            const uint32_t k = d.glob[q];
+            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+        }
     }
     reduce_best(b, width, top);
     if (li == 0) {
@@ -965,6 +1029,7 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
     // searches from every slot
     const uint32_t n = bin ? d.ctl->n_binned : d.ctl->s[p].n_slots;
     const uint32_t t = d.ctl->s[p].t;
+    const uint32_t n_glob = d.link ? d.ctl->n_glob : 0u;
     if (first >= n) return;
     {
         // rows of the species in use, as words; the radii of the rules
@@ -1018,11 +1083,11 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
         if (B)
             per_sim(sim_of(rj.w), [&](uint32_t u) {
                 search_claimer<true>(d, d.tab[u], P, A, t, j, rj, ida, li, int(width), int(wide),
-                                     is_wide, moved, plocal, &nprop, &d.ctl->n_prop[p]);
+                                     is_wide, moved, n_glob, plocal, &nprop, &d.ctl->n_prop[p]);
             });
         else
             search_claimer<false>(d, T, P, A, t, j, rj, ida, li, int(width), int(wide), is_wide,
-                                  moved, plocal, &nprop, &d.ctl->n_prop[p]);
+                                  moved, n_glob, plocal, &nprop, &d.ctl->n_prop[p]);
     }
     // the workgroup's proposers join the step's proposer list (one global
     // atomic per workgroup that has any)
@@ -1046,7 +1111,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     __shared__ uint32_t s_holes;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
-    if (!bin && blockIdx.x == 0 && threadIdx.x == 0) kept_bookkeeping(d, p);
+    if (!bin && blockIdx.x == 0) kept_bookkeeping<B>(d, p, record);
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
     if (blockIdx.x * kBlock >= np) return;
@@ -1160,6 +1225,8 @@ void launch_init(const Dev& d, hipStream_t s)
 void launch_fill_records(const Dev& d, hipStream_t s)
 {
     k_fill_records<<<blocks_for(d.capacity), kBlock, 0, s>>>(d);
+    const uint32_t cells = (d.ntiles << (kScanTileLog + d.tile_shift)) + 1u;
+    k_fill_heads<<<blocks_for(cells), kBlock, 0, s>>>(d, cells);
 }
 template <class K, class... Args>
 static inline void go(K kernel, unsigned grid, unsigned block, hipStream_t s, const KEvents& ev,

@@ -39,7 +39,7 @@ def expected_bin_every(m, G, cap=8):
     (half a cell), the binning is kept only while the claimer species that
     would need 27 cells hold at most an eighth of the initial claimers."""
     bim = [r for r in m.rules if r.kind == W.BIMOL]
-    if not bim or any(r.kind == W.UNIMOL and r.placement != W.KEEP for r in m.rules):
+    if not bim:
         return 1
     f32 = np.float32
     ns = len(m.species)
@@ -156,10 +156,59 @@ def test_live_agent_count_over_kept_steps():
     assert_same(g.export(), h.export(), "kept binning vs every step")
 
 
-def test_models_with_births_or_translocation_bin_every_step():
+def shuttle(n, seed, p_move=0.3):
+    # carriers (A) cross the nuclear membrane at p_move per step each way,
+    # so many cross twice within one kept binning; B binds A on contact in
+    # both compartments, and the complex splits back (births)
+    m = W.c3(n, seed=seed, n_genes=50)
+    sp = [W.Species("A", 0.2, n // 2, W.CYTOPLASM), W.Species("B", 0.2, n - n // 2, W.CYTOPLASM),
+          W.Species("AB", 0.1, 0, W.CYTOPLASM)]
+    rules = [W.unimol(0, -1, p_move, placement=W.TRANSLOCATE, release=0.005,
+                      from_comp=W.CYTOPLASM, to_comp=W.NUCLEUS),
+             W.unimol(0, -1, p_move, placement=W.TRANSLOCATE, release=0.005,
+                      from_comp=W.NUCLEUS, to_comp=W.CYTOPLASM),
+             W.bimol(1, 0, 2, -1, 0.02, 0.7),
+             W.unimol(2, 1, 0.05, placement=W.SPLIT, p2=0, release=0.005)]
+    return m.with_(name="shuttle", species=sp, rules=rules, capacity=n + n // 2 + 4096)
+
+
+PLACING = [
+    ("c1_splits", lambda: W.c1(n_a=6000, n_b=6000, box_um=0.7, unbind_p=0.05), 0.07),
+    ("c3_births_translocation", lambda: W.c3(20_000, seed=41, n_genes=400), 0.4),
+    ("shuttle_placed_twice", lambda: shuttle(12_000, 42), 0.25),
+]
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+@pytest.mark.parametrize("name,make,cell", PLACING, ids=[c[0] for c in PLACING])
+def test_kept_binning_with_placements_is_bit_exact(name, make, cell, graphs):
+    # newborns, translocated agents and split parents join extra chains at
+    # their new cells while a binning is kept; agents placed twice join the
+    # global list; results stay the oracle's
     import paper_2606_14603_amd as mabm
-    for m in (W.c1(n_a=2000, n_b=2000), W.c3(8000, seed=3, n_genes=60)):
-        assert mabm.Sim(m).get_param(mabm.PARAM_BIN_EVERY) == 1
+    m = make()
+    g = mabm.Sim(m, record=True, cell_um=cell, graphs=graphs)
+    G, _ = g.grid()
+    k = g.get_param(mabm.PARAM_BIN_EVERY)
+    say(f"[skin] {name} graphs={graphs} G={G} bin_every={k}")
+    assert k == expected_bin_every(m, G) and k > 1
+    o = oracle.OracleSim(m, grid_n=G)
+    done = 0
+    for c in (1, 2, 3, 7, 16, 33):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        assert_same(g.export(), o.export(), f"{name} t={c}")
+    assert np.array_equal(g.counts()[0], o.counts()[0])
+    assert g.size() == o.size()
+
+
+def test_placing_batch_keeps_binning():
+    import paper_2606_14603_amd as mabm
+    from test_gpu_batch import run_batch
+    models = [W.c3(n, seed=s, n_genes=gn) for n, s, gn in [(9000, 51, 150), (15_000, 52, 300)]]
+    b = run_batch(models, [1, 4, 9, 30])
+    assert b.get_param(mabm.PARAM_BIN_EVERY) > 1
 
 
 def test_limit_changed_mid_run():
