@@ -25,8 +25,9 @@
 // A step that keeps the previous binning (the library allows it while no
 // agent can have moved out of reach of the cell lists it was binned in) is
 // move, propose and finish on the agents in place: move also writes the
-// claimer flags and marks removed agents as holes, and finish's first
-// workgroup does the step's bookkeeping.
+// claimer flags, marks removed agents as holes and chains the agents its
+// rules place into extra per-cell chains, and finish's first workgroup
+// places the step's births (chained too) and does the step's bookkeeping.
 //
 // Cells are sorted by the Morton index of their coordinates, so the cells of
 // a neighbourhood are close in memory.  An agent is a 16-byte record
