@@ -72,6 +72,8 @@ bool config_ok(const mabm_config* c, std::string& why)
         return false;
     }
     if (!(c->dt_s > 0.0f)) { why = "dt_s must be > 0"; return false; }
+    // (slot indices then stay below the extra-chain markers)
+    static_assert((1u << 30) < kUnlinked, "slot indices below the chain markers");
     if (c->capacity == 0 || c->capacity > (1u << 30)) { why = "capacity must be in [1, 2^30]"; return false; }
     if (c->cell_um < 0.0f) { why = "cell_um must be >= 0"; return false; }
     return true;
@@ -367,8 +369,6 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             rmax = std::max(rmax, (double)u.radius_um);
             s->has_bimol = true;
         }
-        if (u.kind == MABM_UNIMOL && (u.placement == MABM_SPLIT || u.placement == MABM_EMIT))
-            T.has_births = 1;
     }
     // unimolecular cumulative thresholds per (species, compartment), rule-id order
     for (int k = 0; k < ns; ++k)

@@ -33,7 +33,6 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kEnd = 0x7FFFFFFFu;
 constexpr uint32_t kUnlinked = 0x7FFFFFFEu;
 constexpr uint32_t kGlobBit = 0x80000000u;
-constexpr uint32_t kMaxSlots = 0x7FFFFFF0u;  // slot indices stay below kUnlinked
 constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
 constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
 constexpr int kScanItems = 8;                 // cells per thread in the scan
@@ -77,7 +76,7 @@ struct Tables {
     uint32_t morton_bits;  // cells are sorted by the Morton (Z-order) index of their
                            // coordinates over a 2^bits grid per axis
     uint32_t key0, key1;   // Philox key (seed low, high)
-    uint32_t has_births, pad;
+    uint32_t pad0, pad1;
     // position of this simulation in a batch (all zero for a single one):
     // its index, its first cell in the batch's cell order, its first slot
     // at placement
