@@ -389,6 +389,21 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
                 T.uni_thr[k][cc][j] = threshold_of(cum);
             }
         }
+    // move's per-(species, compartment) digest of the tables above
+    for (int k = 0; k < ns; ++k)
+        for (int cc = 0; cc < 2; ++cc) {
+            SpecHot& H = T.hot[k][cc];
+            H.sigma = T.sigma[k];
+            H.rmax = T.claim_rmax[k];
+            H.dmax = T.claim_dmax[k];
+            H.claimer = T.claimer[k];
+            H.uni_n = T.uni_n[k][cc];
+            if (H.uni_n) {
+                H.rule0 = T.uni_rule[k][cc][0];
+                H.always = T.uni_thr[k][cc][0] >= (1ull << 32) ? 1 : 0;
+                H.thr0 = H.always ? 0u : (uint32_t)T.uni_thr[k][cc][0];
+            }
+        }
     // spatial hash: G cells per axis, cell size >= 1.01 R_max
     const double ext = extent_of(c);
     uint32_t G = grid_from_config(c);

@@ -68,6 +68,19 @@ struct RuleDev {
     uint64_t thr;    // Bernoulli threshold in [0, 2^32] (BIMOL)
 };
 
+// What move needs of a species in a compartment, in one 32-byte read: its
+// step sigma, its first unimolecular rule and that rule's threshold
+// (`always` when it is 2^32), and, as a claimer, its largest contact radius
+// and its targets' largest move per step.
+struct SpecHot {
+    float sigma;
+    uint32_t thr0;
+    float rmax, dmax;
+    uint8_t uni_n, rule0, claimer, always;
+    uint32_t pad[3];
+};
+static_assert(sizeof(SpecHot) == 32, "one 32-byte read");
+
 struct Tables {
     int32_t geometry, ncomp, ns, nr;
     float L, halfL, Rout, Rout2, Rin, Rin2;
@@ -95,6 +108,7 @@ struct Tables {
     uint64_t uni_thr[kMaxSpecies][2][kMaxUni];
     int8_t rule_of[kMaxSpecies][kMaxSpecies];
     RuleDev rule[kMaxRules];
+    SpecHot hot[kMaxSpecies][2];  // [species][compartment], from the fields above
 };
 
 // Step scalars are double-buffered by parity p = t mod 2 (the buffer the
@@ -138,7 +152,8 @@ struct Dev {
     Agents a[2];          // ping-pong agent arrays
     uint32_t* rank;       // per pre-sort slot: rank in its cell (kNone: not binned)
     uint8_t* event;       // per pre-sort slot: event rule (record mode)
-    uint8_t* sclaim;      // per sorted agent: 1 = claimer this step
+    uint8_t* sclaim;      // per agent slot: 1 = claimer this step, 2 = one searching
+                          // the 27-cell stencil while the others search 8
     uint32_t* cell_count;  // ncells rounded up to whole scan tiles
     uint32_t* cell_start;  // padded ncells + 1
     uint32_t* tile_acc;    // [2][ntiles * kTileStride]: cell-count sums per scan tile,

@@ -249,19 +249,26 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
     const U4 w = draw(T, id, t, kMove, 0u);
 
     int ev = -1;
-    const int nu = T.uni_n[s][c0];
+    const SpecHot H = T.hot[s][c0];
+    const int nu = H.uni_n;
     if (nu) {
+        // the cumulative thresholds in rule order: the first from the
+        // digest, any further ones from the full table
         const uint32_t wu = event_bits(w);
-        for (int j = 0; j < nu; ++j)
-            if (uint64_t(wu) < T.uni_thr[s][c0][j]) {
-                ev = T.uni_rule[s][c0][j];
-                break;
-            }
+        if (H.always || wu < H.thr0) {
+            ev = H.rule0;
+        } else {
+            for (int j = 1; j < nu; ++j)
+                if (uint64_t(wu) < T.uni_thr[s][c0][j]) {
+                    ev = T.uni_rule[s][c0][j];
+                    break;
+                }
+        }
     }
 
     float z0, z1, z2;
     normals3(w, z0, z1, z2);
-    const float sg = T.sigma[s];
+    const float sg = H.sigma;
     float x1 = __builtin_fmaf(sg, z0, x), y1 = __builtin_fmaf(sg, z1, y), w1 = __builtin_fmaf(sg, z2, z);
     if (T.geometry == kBox) {
         x1 = wrap_box(T, x1);
@@ -354,9 +361,10 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
         A.rec[i] = make_rec(fx, fy, fz, meta);
         if (record) d.event[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
     } else {
-        const bool claim = ev < 0 && T.claimer[fs];
-        const bool wide =
-            T.stencil8 && (T.claim_rmax[fs] + float(moved) * T.claim_dmax[fs]) * T.inv_h > 0.495f;
+        // the final species' claimer data (a conversion changed it rarely)
+        const SpecHot& F = fs == s ? H : T.hot[fs][0];
+        const bool claim = ev < 0 && F.claimer;
+        const bool wide = T.stencil8 && (F.rmax + float(moved) * F.dmax) * T.inv_h > 0.495f;
         A.rec[i] = make_rec(fx, fy, fz, meta | (claim ? kMetaClaimer : 0u));
         d.sclaim[i] = claim ? (wide ? 2 : 1) : 0;
         if (record) {
