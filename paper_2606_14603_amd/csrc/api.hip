@@ -177,7 +177,7 @@ struct mabm_sim {
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
-    // captured steps (one step, and kGraphSteps steps) per starting state:
+    // captured steps (one step, and graph_steps steps) per starting state:
     // parity, agent buffer and steps since the last binning
     std::map<uint32_t, hipGraphExec_t> graphs;
     int parity = 0;
@@ -870,9 +870,18 @@ void enqueue_step(mabm_sim* s, int p, int buf, bool bin, uint32_t moved)
 // Capture `steps` consecutive steps from the current schedule state as one graph on
 // the caller's stream (kernel nodes only: the step has no memset or copy).
 // Long runs replay the multi-step graph, so the host issues one launch per
-// kGraphSteps steps; that matters for small simulations, whose steps take
-// about as long to enqueue as to run.
+// graph_steps steps; that matters for small simulations, whose steps take
+// about as long to enqueue as to run.  The multi-step graph spans at least
+// 16 steps and a whole number of pairs of binning cycles, so it ends in the
+// state it starts from (parity, buffer, steps since the binning) and one
+// capture serves the whole run.
 constexpr uint32_t kGraphSteps = 16;
+
+uint32_t graph_steps(const mabm_sim* s)
+{
+    const uint32_t cycle = 2 * s->bin_every;
+    return (kGraphSteps + cycle - 1) / cycle * cycle;
+}
 
 // Advances the schedule state (parity, buffer, steps kept) by one step;
 // returns whether that step bins.
@@ -937,8 +946,9 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
         const uint64_t until_rec =
             s->ring_every ? s->ring_every - s->steps_done % s->ring_every : ~0ull;
         if (graphs) {
-            const uint32_t kind = (n_steps - k >= kGraphSteps && until_rec >= kGraphSteps) ? 1 : 0;
-            m = kind ? kGraphSteps : 1u;
+            const uint32_t L = graph_steps(s);
+            const uint32_t kind = (n_steps - k >= L && until_rec >= L) ? 1 : 0;
+            m = kind ? L : 1u;
             const uint32_t key = kind | uint32_t(s->parity) << 1 | uint32_t(s->buf) << 2 | s->kept << 3;
             hipGraphExec_t& g = s->graphs[key];
             if (!g) {
