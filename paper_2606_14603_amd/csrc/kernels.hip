@@ -1,26 +1,28 @@
 // kernels.hip -- the per-step kernels of the molecule-agent update for
-// gfx950 (wave64).  One step (O2..O10 of the step definition) of parity p
-// (agents start in buffer p and are sorted into buffer p ^ 1) is five
-// launches:
+// gfx950 (wave64).  A binning step (O2..O10 of the step definition) of
+// parity p (agents start in buffer p and are sorted into buffer p ^ 1) is
+// five launches:
 //
 //   move     one Philox block per agent gives the event draw and the
 //            Brownian step; boundaries, event effects, birth records; the
 //            cell key of the moved position and its rank in the cell, by one
 //            atomic per run of equal keys in a wave (agents arrive sorted by
-//            cell from the previous step, so runs are long and the atomics
-//            spread over many cells), and the per-tile sums of the counts
-//            the same way
-//   scan     each tile of 2048 cells adds the sums of the tiles before it,
-//            scans its counts into cell starts and clears them
+//            cell from the previous binning, so runs are long and the
+//            atomics spread over many cells), and the per-tile sums of the
+//            counts the same way
+//   scan     each tile (2,048 cells, or a power of two times that) adds the
+//            sums of the tiles before it, scans its counts into cell starts
+//            and clears them
 //   scatter  agents to cell order in the other buffer (holes and degraded
 //            agents dropped: stream compaction); one extra workgroup ranks
 //            the step's births by parent id, appends them with fresh ids and
 //            writes the next step's scalars
-//   propose  per workgroup, a chunk of 512 sorted agents: its claimers are
-//            compacted in LDS, then each is searched by a subgroup of lanes,
-//            one stencil cell per lane, for the nearest eligible partner;
+//   propose  per workgroup, a chunk of 1,024 sorted agents (or a share of
+//            one): its claimers are compacted in LDS, 27-cell ones first,
+//            then each is searched by a group of 4 lanes (16 for 27 cells),
+//            two stencil cells per lane, for the nearest eligible partner;
 //            Bernoulli draw; handshake keys into both claim slots
-//   finish   per chunk: confirmation and pair products
+//   finish   over the step's proposals: confirmation and pair products
 //
 // A step that keeps the previous binning (the library allows it while no
 // agent can have moved out of reach of the cell lists it was binned in) is
@@ -811,7 +813,7 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
 
 // ---------------------------------------------------------------------------
 // propose (O7): for each claimer, the eligible partner minimising (d^2, id)
-// over the 8-cell (h >= 2 R_max) or 27-cell stencil, then a Bernoulli draw,
+// over its 8-cell or 27-cell stencil, then a Bernoulli draw,
 // then the handshake key into both claim slots by atomic minimum.  A
 // workgroup takes 1024 sorted agents; their claimers are searched by
 // subgroups of 4 (or 16) lanes, two stencil cells per lane, and the lanes'
