@@ -28,11 +28,12 @@ __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // one 32x32->64 multiply-add per product gives both halves
+        // one 32x32->64 multiply-add per product gives both halves; each
+        // three-way xor is one three-input bit operation (truth table 0x96)
         const uint64_t pa = uint64_t(kMulA) * c0;
         const uint64_t pb = uint64_t(kMulB) * c2;
-        const uint32_t n0 = uint32_t(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = uint32_t(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(pb >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(pa >> 32), c3, k1, 0x96);
         c0 = n0;
         c1 = uint32_t(pb);
         c2 = n2;
@@ -102,14 +103,15 @@ __device__ __forceinline__ void sincos_turn(float a, float& sn, float& cs)
     pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
     pc = __builtin_fmaf(pc, x2, -0.5f);
     const float cx = __builtin_fmaf(pc, x2, 1.0f);
-    const float s1 = fold ? cx : sx;
-    const float c1 = fold ? sx : cx;
-    switch (quad & 3) {
-    case 0: sn = s1; cs = c1; break;
-    case 1: sn = c1; cs = -s1; break;
-    case 2: sn = -s1; cs = -c1; break;
-    default: sn = -c1; cs = s1; break;
-    }
+    // quadrant q in 0..3: (sin, cos) = (s1, c1), (c1, -s1), (-s1, -c1),
+    // (-c1, s1), with s1, c1 the folded pair; as selects and sign-bit flips
+    // (negation is the sign flip), without branches
+    const uint32_t q = uint32_t(quad);
+    const bool swap = fold != ((q & 1u) != 0u);
+    const float sv = swap ? cx : sx;
+    const float cv = swap ? sx : cx;
+    sn = __uint_as_float(__float_as_uint(sv) ^ ((q & 2u) << 30));
+    cs = __uint_as_float(__float_as_uint(cv) ^ (((q + 1u) & 2u) << 30));
 }
 
 // The 32-bit event draw: the four low bytes of the MOVE block, word 0
@@ -160,10 +162,10 @@ __device__ __forceinline__ bool admissible(const Tables& T, float x, float y, fl
 
 __device__ __forceinline__ uint32_t cell_coord(const Tables& T, float v)
 {
+    // clamped to [0, G-1] (fmaxf takes the number over a NaN, so a NaN
+    // coordinate maps to cell 0), then converted exactly
     const float f = __builtin_floorf((v - T.lo) * T.inv_h);
-    if (!(f >= 0.0f)) return 0u;
-    if (f >= float(T.G)) return T.G - 1u;
-    return uint32_t(f);
+    return uint32_t(fminf(fmaxf(f, 0.0f), float(T.G - 1u)));
 }
 
 // Morton (Z-order) index: the bits of the three 10-bit cell coordinates
