@@ -24,11 +24,13 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(out: str = LIB_PATH, extra: list[str] | None = None, verbose: bool = False) -> str:
+def build(out: str = LIB_PATH, extra: list[str] | None = None, verbose: bool = False,
+          sources: list[str] | None = None) -> str:
+    """Compile `sources` (default: the library's) into the shared object `out`."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = out + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, *(extra or []), f"-I{os.path.join(ROOT, 'include')}",
-           *SOURCES, "-o", tmp]
+           *(sources or SOURCES), "-o", tmp]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)

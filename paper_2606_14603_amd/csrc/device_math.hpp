@@ -5,7 +5,9 @@
 // binary32 +, -, *, /, sqrt and explicit fused multiply-add (the library is
 // built with -ffp-contract=off, so no other operation is fused; denormals
 // are kept, division and square root correctly rounded), so every result is
-// reproducible bit for bit from the step definition.
+// reproducible bit for bit from the step definition.  Box-Muller's quotient
+// and roots take shorter sequences that equal the correctly rounded
+// operation on the arguments they can receive.
 #pragma once
 
 #include "engine.hpp"
@@ -54,6 +56,42 @@ __device__ __forceinline__ U4 draw(const Tables& T, uint32_t c0, uint32_t c1, ui
 __device__ __forceinline__ float u01(uint32_t w) { return float(w >> 8) * 0x1p-24f; }
 __device__ __forceinline__ float u01_open0(uint32_t w) { return float((w >> 8) + 1u) * 0x1p-24f; }
 
+// a / b for the quotient of ln_unit below: a = m - 1 and b = m + 1 with m
+// a float in [0.70, 1.42], so b lies in [1.7, 2.5] and the quotient is zero
+// or normal.  The reciprocal estimate of the hardware is refined by one
+// Newton step, and the quotient by two corrections with its residual,
+// which a fused multiply-add gives exactly.  No operand scaling or
+// special-value fix-up is needed in that range; the result equals the
+// correctly rounded quotient for every such m (an exhaustive device test
+// compares the two over all of them).
+__device__ __forceinline__ float div_log_quotient(float a, float b)
+{
+    float y = __builtin_amdgcn_rcpf(b);
+    y = __builtin_fmaf(__builtin_fmaf(-b, y, 1.0f), y, y);
+    float q = a * y;
+    q = __builtin_fmaf(__builtin_fmaf(-b, q, a), y, q);
+    return __builtin_fmaf(__builtin_fmaf(-b, q, a), y, q);
+}
+
+// Square root of x = 0 or x in [2^-96, 64] (the Box-Muller radius: x =
+// -2 ln u <= 34): the hardware estimate y is within one unit in the last
+// place, and the correctly rounded root is the candidate c among y - ulp,
+// y, y + ulp with (c - ulp/2)^2 < x < (c + ulp/2)^2.  Since x and the
+// products of candidates are multiples of ulp^2, the two bounds are
+// decided exactly by the signs of the fused residuals x - (y - ulp) y and
+// x - y (y + ulp).  Equal to the correctly rounded root over the whole
+// range (exhaustive device test).
+__device__ __forceinline__ float sqrt_radius(float x)
+{
+    const float y = __builtin_amdgcn_sqrtf(x);
+    const float below = __uint_as_float(__float_as_uint(y) - 1u);
+    const float above = __uint_as_float(__float_as_uint(y) + 1u);
+    float r = y;
+    if (__builtin_fmaf(-below, y, x) <= 0.0f) r = below;
+    if (__builtin_fmaf(-above, y, x) > 0.0f) r = above;
+    return r;
+}
+
 // ln x for x in (0, 1]: split x = m 2^e, fold m above sqrt 2 down by one
 // octave, then ln m = 2 atanh(s) with s = (m-1)/(m+1) and the odd series of
 // atanh through s^9 by Horner's rule with fused multiply-adds; e ln 2 is
@@ -67,7 +105,7 @@ __device__ __forceinline__ float ln_unit(float x)
         m = m * 0.5f;
         e = e + 1;
     }
-    const float s = (m - 1.0f) / (m + 1.0f);
+    const float s = div_log_quotient(m - 1.0f, m + 1.0f);
     const float s2 = s * s;
     float h = 1.0f / 9.0f;
     h = __builtin_fmaf(h, s2, 1.0f / 7.0f);
@@ -125,11 +163,11 @@ __device__ __forceinline__ uint32_t event_bits(const U4& w)
 __device__ __forceinline__ void normals3(const U4& w, float& z0, float& z1, float& z2)
 {
     float sn, cs;
-    const float r1 = __builtin_sqrtf(-2.0f * ln_unit(u01_open0(w.w0)));
+    const float r1 = sqrt_radius(-2.0f * ln_unit(u01_open0(w.w0)));
     sincos_turn(u01(w.w1), sn, cs);
     z0 = r1 * cs;
     z1 = r1 * sn;
-    const float r2 = __builtin_sqrtf(-2.0f * ln_unit(u01_open0(w.w2)));
+    const float r2 = sqrt_radius(-2.0f * ln_unit(u01_open0(w.w2)));
     sincos_turn(u01(w.w3), sn, cs);
     z2 = r2 * cs;
 }
