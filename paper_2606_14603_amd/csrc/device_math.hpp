@@ -30,12 +30,21 @@ __device__ __forceinline__ U4 philox(uint32_t k0, uint32_t k1, uint32_t c0, uint
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // one 32x32->64 multiply-add per product gives both halves; each
-        // three-way xor is one three-input bit operation (truth table 0x96)
+        // one 32x32->64 multiply-add per product gives both halves; after
+        // the first round each three-way xor is one three-input bit
+        // operation (truth table 0x96).  The first round keeps plain xors:
+        // with a step-uniform counter word its word 0 is wave-uniform, and
+        // it stays in scalar registers, as does the next round's product.
         const uint64_t pa = uint64_t(kMulA) * c0;
         const uint64_t pb = uint64_t(kMulB) * c2;
-        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(uint32_t(pb >> 32), c1, k0, 0x96);
-        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(uint32_t(pa >> 32), c3, k1, 0x96);
+        uint32_t n0, n2;
+        if (r == 0) {
+            n0 = uint32_t(pb >> 32) ^ c1 ^ k0;
+            n2 = uint32_t(pa >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = __builtin_amdgcn_bitop3_b32(uint32_t(pb >> 32), c1, k0, 0x96);
+            n2 = __builtin_amdgcn_bitop3_b32(uint32_t(pa >> 32), c3, k1, 0x96);
+        }
         c0 = n0;
         c1 = uint32_t(pb);
         c2 = n2;
