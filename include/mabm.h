@@ -265,10 +265,11 @@ mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
 /* MABM_PARAM_BIN_EVERY_MAX: the most steps between two binnings of the
  * agents into cells (0: the library's limit, 8; 1: every step).  Between
  * binnings agents keep their array slots and the neighbour search reads the
- * last binning's cell lists; the library bins only as rarely as keeps every
- * result unchanged (every contact radius plus the largest possible Brownian
- * moves since the binning within the stencil's reach, and never for models
- * with births or translocations).  Results do not depend on it. */
+ * last binning's cell lists (agents that rules place since the binning are
+ * listed apart); the library bins only as rarely as keeps every result
+ * unchanged (every contact radius plus the largest possible Brownian moves
+ * since the binning within the stencil's reach), and every step for models
+ * without pair rules.  Results do not depend on it. */
 #define MABM_PARAM_BIN_EVERY_MAX 3
 /* MABM_PARAM_BIN_EVERY (mabm_get_param only): steps between binnings in
  * effect (finalizes the model). */
