@@ -820,6 +820,9 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
 // best candidates are reduced by shuffles, so each claimer's dependent
 // chain of loads is a few round trips long.
 // ---------------------------------------------------------------------------
+// rule: the pair rule's index, plus kBestClaimer when the candidate is a
+// claimer itself this step (finish's mutual-pair test needs it)
+constexpr int kBestClaimer = 0x100;
 struct Best {
     uint32_t idx, id;
     float d2;
@@ -863,7 +866,7 @@ __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, cons
         b.idx = k;
         b.id = bid;
         b.d2 = d2;
-        b.rule = r;
+        b.rule = r | ((rk.w & kMetaClaimer) ? kBestClaimer : 0);
     }
 }
 
@@ -995,7 +998,7 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         uint32_t out = kNone;
         if (b.idx != kNone) {
             const uint32_t w = draw(T, ida, t, kPair, 0u).w0;
-            if (uint64_t(w) < T.rule[b.rule].thr) {
+            if (uint64_t(w) < T.rule[b.rule & 0xFF].thr) {
                 const uint32_t lo_id = ida < b.id ? ida : b.id, hi_id = ida < b.id ? b.id : ida;
                 const unsigned long long pr =
                     (unsigned long long)draw(T, lo_id, t, kPrio, hi_id).w0 << 32;
@@ -1005,7 +1008,10 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
                 // the proposal, staged in LDS for the workgroup's one
                 // reservation in the step's list (the rare overflow
                 // reserves its own entry)
-                const uint4 e{j, b.idx, ida, b.id};
+                // {claimer, target, claimer id, rule | target claims <<
+                // 8 | simulation << 16}: what finish needs besides the
+                // slots and the target's id
+                const uint4 e{j, b.idx, ida, uint32_t(b.rule & 0x1FF) | (T.sim << 16)};
                 const uint32_t k = atomicAdd(nprop, 1u);
                 if (k < kPropLds) plocal[k] = e;
                 else d.plist[atomicAdd(n_prop, 1u)] = e;
@@ -1113,8 +1119,9 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
 // ---------------------------------------------------------------------------
 // finish: O7 confirmation and O8 pair products (only the claimer of a
 // confirmed pair writes, and of a mutual homotypic pair only the lower id).
-// Species are written as single bytes, so the flag byte of the same record,
-// which another thread may be testing, is never rewritten.
+// The proposer entry carries the rule and whether the target claims too, so
+// a confirmation reads only the two slots and the target's id and proposal.
+// Species are written as single bytes, leaving the flag bytes alone.
 // ---------------------------------------------------------------------------
 template <bool B>
 __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int bin)
@@ -1123,30 +1130,33 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
     if (!bin && blockIdx.x == 0) kept_bookkeeping<B>(d, p, record);
+    // the thread's first proposer entry is requested with the list's length
+    // (entries past it are stale but inside the list's capacity)
+    uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    uint4 e = q < d.capacity ? d.plist[q] : uint4{};
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
     if (blockIdx.x * kBlock >= np) return;
     if (threadIdx.x == 0) s_holes = 0;
     __syncthreads();
     const Agents A = d.a[p ^ 1];
-    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < np; q += gridDim.x * kBlock) {
-        const uint4 e = d.plist[q];
-        const uint32_t j = e.x, b = e.y, ida = e.z, idb = e.w;
-        // everything the confirmation and the products need, requested
-        // together (no other thread writes the species of a confirmed
-        // pair, and the flag byte is never rewritten)
-        const uint32_t wj = A.rec[j].w, wb = A.rec[b].w, pb = d.prop[b];
+    for (; q < np; q += gridDim.x * kBlock) {
+        if (q >= blockIdx.x * kBlock + kBlock) e = d.plist[q];
+        const uint32_t j = e.x, b = e.y, ida = e.z;
+        const int rule = int(e.w & 0xFFu);
+        const bool b_claims = (e.w & uint32_t(kBestClaimer)) != 0;
+        // the slots, the target's id and proposal, requested together
+        const uint32_t idb = A.id[b], pb = d.prop[b];
         const unsigned long long slot_j = d.slot[j], slot_b = d.slot[b];
         const uint32_t lo_id = ida < idb ? ida : idb, hi_id = ida < idb ? idb : ida;
         // the pair's simulation gives the Philox key
-        const Tables& Tk = B ? d.tab[sim_of(wj)] : T;
+        const Tables& Tk = B ? d.tab[e.w >> 16] : T;
         const unsigned long long pr = (unsigned long long)draw(Tk, lo_id, t, kPrio, hi_id).w0 << 32;
         if (slot_j != (pr | idb) || slot_b != (pr | ida)) continue;
         // b proposed too only if it carries the claimer flag (its prop is
         // then this step's); a mutual pair fires once, from the lower id
-        if (idb < ida && (wb & kMetaClaimer) && pb == j) continue;
-        const uint32_t sj = wj & 0xFFu, sb = wb & 0xFFu;
-        const RuleDev& R = T.rule[T.rule_of[sj][sb]];
+        if (idb < ida && b_claims && pb == j) continue;
+        const RuleDev& R = T.rule[rule];
         set_species(A, j, R.p0 < 0 ? kDead : uint32_t(R.p0));
         set_species(A, b, R.p1 < 0 ? kDead : uint32_t(R.p1));
         const uint32_t h = (R.p0 < 0 ? 1u : 0u) + (R.p1 < 0 ? 1u : 0u);
