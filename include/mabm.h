@@ -171,8 +171,12 @@ mabm_status mabm_export(mabm_sim* sim, uint32_t capacity, uint32_t* id, uint8_t*
                         uint32_t* partner);
 
 /* Replace the initial placement (or resume a checkpoint): n agents with the
- * given ids (all < next_id), species and positions (inside the volume), and
- * the step counter t.  Finalizes the model.  Synchronises. */
+ * given ids (distinct, all < next_id), species and positions (inside the
+ * volume), and the step counter t.  E_INVALID for a null array (n > 0), an
+ * unknown species, a repeated id, an id not below next_id or a position
+ * outside the volume; E_CAPACITY for n above the capacity; E_STATE after
+ * the model was finalized or on a batch.  Finalizes the model.
+ * Synchronises. */
 mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uint8_t* species,
                         const float* x, const float* y, const float* z, uint32_t next_id,
                         uint32_t t);

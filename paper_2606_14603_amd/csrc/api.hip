@@ -979,6 +979,7 @@ mabm_status mabm_step(mabm_sim* s, uint32_t n_steps)
 mabm_status mabm_counts(mabm_sim* s, uint64_t* out, uint32_t n_species, uint64_t* out_step)
 {
     if (!s) return MABM_E_INVALID;
+    if (!out && n_species) return fail(s, MABM_E_INVALID, "null counts array");
     mabm_status st = finalize(s, true);
     if (st != MABM_OK) return st;
     if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
@@ -1108,10 +1109,9 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
     if (is_batch(s, "mabm_import")) return MABM_E_STATE;
     if (s->finalized) return fail(s, MABM_E_STATE, "import after the model was finalized");
     if (n > s->cfg.capacity) return fail(s, MABM_E_CAPACITY, "import exceeds the capacity");
+    if (n && (!id || !sp || !x || !y || !z)) return fail(s, MABM_E_INVALID, "null import array");
     const mabm_config& c = s->cfg;
     const float Rout2 = (float)((double)c.outer_radius_um * (double)c.outer_radius_um);
-    const float Rin2 = (float)((double)c.inner_radius_um * (double)c.inner_radius_um);
-    (void)Rin2;
     for (uint32_t i = 0; i < n; ++i) {
         if (sp[i] >= s->species.size()) return fail(s, MABM_E_INVALID, "unknown species in import");
         if (id[i] >= next_id) return fail(s, MABM_E_INVALID, "id not below next_id");
@@ -1122,6 +1122,13 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
         } else if (!(x[i] * x[i] + y[i] * y[i] + z[i] * z[i] <= Rout2)) {
             return fail(s, MABM_E_INVALID, "imported position outside the volume");
         }
+    }
+    {
+        // ids key every random draw, so each may appear once
+        std::vector<uint32_t> ids(id, id + n);
+        std::sort(ids.begin(), ids.end());
+        if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+            return fail(s, MABM_E_INVALID, "duplicate id in import");
     }
     mabm_status st = finalize(s, false);
     if (st != MABM_OK) return st;

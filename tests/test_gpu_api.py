@@ -86,3 +86,25 @@ def test_agent_updates_and_profile(mabm):
     assert s.agent_updates() >= 10 * 19_000
     n, _ = s.size()
     assert n <= 20_000
+
+
+def test_import_validation(mabm):
+    m = W.c1(n_a=10, n_b=10, box_um=0.5)
+    ids = np.arange(4, dtype=np.uint32)
+    sp = np.zeros(4, np.uint8)
+    x = np.full(4, 0.1, np.float32)
+    cases = [
+        (np.array([0, 1, 1, 3], np.uint32), sp, x, 10, "duplicate"),
+        (ids, sp, x, 3, "next_id"),
+        (ids, np.array([0, 0, 9, 0], np.uint8), x, 10, "species"),
+        (ids, sp, np.array([0.1, 0.1, 0.6, 0.1], np.float32), 10, "outside"),
+    ]
+    for i, s_, xx, nid, what in cases:
+        s = mabm.Sim(m)
+        with pytest.raises(mabm.MabmError) as e:
+            s.import_state(i, s_, xx, x, x, next_id=nid)
+        assert e.value.code == mabm.E_INVALID, what
+        s.close()
+    s = mabm.Sim(m)
+    s.import_state(ids, sp, x, x, x, next_id=10)
+    assert s.size() == (4, 10)
