@@ -339,7 +339,7 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             for (int b = 0; b < ns; ++b)
                 if (becomes[a][m] && becomes[m][b]) becomes[a][b] = true;
     for (int a = 0; a < kMaxSpecies; ++a)
-        for (int b = 0; b < kMaxSpecies; ++b) T.rule_of[a][b] = -1;
+        for (int b = 0; b < kMaxSpecies; ++b) T.rule_of[a][b] = kNoRule;
     double rmax = 0.0;
     s->has_bimol = false;
     for (int r = 0; r < nr; ++r) {
@@ -358,7 +358,7 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
             R.target_r = (float)(u.to_comp == 0 ? (double)c.inner_radius_um - (double)u.release_radius_um
                                                 : (double)c.inner_radius_um + (double)u.release_radius_um);
         if (u.kind == MABM_BIMOL) {
-            T.rule_of[u.reactant[0]][u.reactant[1]] = (int8_t)r;
+            T.rule_of[u.reactant[0]][u.reactant[1]] = (uint8_t)r;
             T.claimer[u.reactant[0]] = 1;
             T.claim_r2max[u.reactant[0]] = std::max(T.claim_r2max[u.reactant[0]], R.r2);
             T.claim_rmax[u.reactant[0]] = std::max(T.claim_rmax[u.reactant[0]], u.radius_um);

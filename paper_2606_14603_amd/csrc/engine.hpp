@@ -14,6 +14,8 @@ constexpr int kMaxRules = 255;
 constexpr int kMaxUni = 8;        // unimolecular rules per (species, compartment)
 constexpr uint8_t kDead = 0xFF;   // species byte of a consumed agent (hole)
 constexpr uint8_t kNoEvent = 0xFF;
+constexpr uint8_t kNoRule = 0xFF;  // no pair rule (rule indices run to kMaxRules - 1)
+static_assert(kMaxRules <= 255, "rule indices fit a byte beside kNoRule");
 // An agent is a 16-byte record {x, y, z, meta} (position bits, then
 // species in bits 0-7, this step's flags in bits 8-15 and, in a batch, the
 // index of the agent's simulation in bits 16-31) plus its id in a separate
@@ -106,7 +108,7 @@ struct Tables {
     uint8_t uni_n[kMaxSpecies][2];
     uint8_t uni_rule[kMaxSpecies][2][kMaxUni];
     uint64_t uni_thr[kMaxSpecies][2][kMaxUni];
-    int8_t rule_of[kMaxSpecies][kMaxSpecies];
+    uint8_t rule_of[kMaxSpecies][kMaxSpecies];  // pair rule of (claimer, target), kNoRule: none
     RuleDev rule[kMaxRules];
     SpecHot hot[kMaxSpecies][2];  // [species][compartment], from the fields above
 };

@@ -832,7 +832,7 @@ struct Best {
 // The pair-rule table and the contact radii live in LDS while a workgroup
 // searches: rule index of (claimer species, target species), -1 for none.
 struct PairLds {
-    int8_t rule_of[kMaxSpecies * kMaxSpecies];
+    uint8_t rule_of[kMaxSpecies * kMaxSpecies];
     float r2[kMaxRules];
     float r2max[kMaxSpecies];  // per claimer species, its largest r2
     float rmax[kMaxSpecies];   // and its largest contact radius
@@ -856,7 +856,8 @@ __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, cons
     // every candidate stops here, before the rule lookup
     if (!(d2 <= r2max)) return;
     const uint32_t sb = rk.w & 0xFFu;
-    const int r = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : -1;
+    const uint32_t rv = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : kNoRule;
+    const int r = rv == kNoRule ? -1 : int(rv);
     if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
     if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
     if (!(d2 <= P.r2[r])) return;

@@ -214,3 +214,42 @@ def test_dense_box_overflows_the_workgroup_proposal_stage():
         done = c
         assert_same(g.export(), o.export(), f"dense box t={c}")
     assert o.counts()[0][2] > 2000
+
+
+def largest_tables(seed=7):
+    """64 species and 255 rules, the library's table limits: 180 pair rules
+    over distinct unordered species pairs (a few homotypic, some consuming
+    the target), and 75 unimolecular conversions and degradations, eight on
+    each of the first nine species (the most one species takes), in a
+    sphere at the cascade's density."""
+    rng = np.random.default_rng(seed)
+    ns = 64
+    sp = [W.Species(f"s{k}", float(rng.uniform(0.2, 3.0)), 300) for k in range(ns)]
+    pairs = set()
+    rules = []
+    while len(rules) < 180:
+        a, b = (int(v) for v in rng.integers(0, ns, 2))
+        if len(pairs) < 6:
+            b = a
+        key = (min(a, b), max(a, b))
+        if key in pairs:
+            continue
+        pairs.add(key)
+        p1 = int(rng.integers(0, ns))
+        p2 = -1 if rng.random() < 0.3 else int(rng.integers(0, ns))
+        rules.append(W.bimol(a, b, p1, p2, float(rng.uniform(0.005, 0.015)),
+                             float(rng.uniform(0.3, 1.0))))
+    for k in range(75):
+        a = k // 8 if k < 72 else 9
+        p1 = -1 if k % 5 == 0 else int(rng.integers(0, ns))
+        rules.append(W.unimol(a, p1, 0.01))
+    n = 300 * ns
+    radius = (n / 2000.0 * 3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+    return W.Model("largest_tables", W.SPHERE, 1e-6, seed, sp, rules,
+                   outer_radius_um=float(radius), capacity=n + 256, steps=40)
+
+
+def test_largest_tables_match_oracle():
+    m = largest_tables()
+    assert len(m.species) == 64 and len(m.rules) == 255
+    run_pair(m, [1, 2, 5, 20, 40])
