@@ -253,3 +253,16 @@ def test_largest_tables_match_oracle():
     m = largest_tables()
     assert len(m.species) == 64 and len(m.rules) == 255
     run_pair(m, [1, 2, 5, 20, 40])
+
+
+def test_largest_grid_matches_oracle():
+    # 512 cells per axis, the library's largest grid: 27-bit Morton keys and
+    # scan tiles of 2^6 passes (134M cells in at most 1,024 tiles)
+    # (20k cascade agents in a 2.7 um sphere: 10.5 nm cells, just above the
+    # largest contact radius)
+    import paper_2606_14603_amd as mabm
+    m = W.c2(20_000, seed=8, steps=6).with_(outer_radius_um=2.7)
+    g = mabm.Sim(m, record=True, cell_um=0.01054)
+    assert g.grid()[0] == 512
+    g.close()
+    run_pair(m, [1, 3, 6], cell_um=0.01054)
