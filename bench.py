@@ -78,9 +78,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
 TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "25c7726f3279df1c176c57f0fbd086ff353e8b4e38c09abfe6899a90db96e903",
+           "sources_sha256": "79820a51a5c7a53bac57be995a58115a5a934a337b8c2a59434360d78a2da6e9",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19630.3, 40070.9), "scan": (4631.8, 16416.1), "scatter": (34501.4, 56202.9), "propose": (17822.8, 2952.0), "finish": (154.5, 0.5)}}
+           "kib": {"move": (19628.3, 40070.4), "scan": (4631.8, 16416.1), "scatter": (34493.4, 56192.5), "propose": (17822.3, 2952.0), "finish": (152.5, 0.5)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
