@@ -991,7 +991,10 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
             consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
         for (uint32_t q = uint32_t(li); q < n_glob; q += uint32_t(width)) {
             const uint32_t k = d.glob[q];
-            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+            const uint4 rk = A.rec[k];
+            // a batch's global list holds the agents of every simulation
+            if (B && sim_of(rk.w) != T.sim) continue;
+            consider(T, P, A, rk, k, j, s, x, y, z, comp, r2max, b);
         }
     }
     reduce_best(b, width, top);

@@ -1,0 +1,131 @@
+"""Randomised models against the oracle: geometry, species (some that never
+move), pair rules (homotypic ones, products that are consumed, contact
+probabilities of 0 and 1) and unimolecular rules of every placement
+(conversions, degradations, splits and emissions with release radii large
+enough that many placements are rejected near walls and membranes,
+translocations both ways), dense enough that claims conflict.  The GPU must
+match the oracle bit for bit on every one, with the cell lists kept between
+binnings as the library chooses and with binning every step."""
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import run_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_14603_amd as mabm
+    mabm.lib()
+
+
+def random_model(seed: int) -> W.Model:
+    rng = np.random.default_rng(seed)
+    geometry = [W.PERIODIC_BOX, W.SPHERE, W.NESTED_SPHERES][seed % 3]
+    ncomp = 2 if geometry == W.NESTED_SPHERES else 1
+    ns = int(rng.integers(3, 13))
+    n = int(rng.integers(1500, 4000))
+    counts = rng.multinomial(n, rng.dirichlet(np.ones(ns)))
+    species = []
+    for k in range(ns):
+        d = 0.0 if rng.random() < 0.2 else float(rng.uniform(0.1, 5.0))
+        species.append(W.Species(f"s{k}", d, int(counts[k]), int(rng.integers(0, ncomp))))
+    rules = []
+    pairs = set()
+    for _ in range(int(rng.integers(1, 2 * ns))):
+        a, b = (int(v) for v in rng.integers(0, ns, 2))
+        if rng.random() < 0.15:
+            b = a
+        if (min(a, b), max(a, b)) in pairs:
+            continue
+        pairs.add((min(a, b), max(a, b)))
+        p = [0.0, 1.0, float(rng.uniform(0.05, 1.0))][int(rng.integers(0, 3))]
+        p1 = int(rng.integers(-1, ns))
+        p2 = int(rng.integers(-1, ns))
+        rules.append(W.bimol(a, b, p1, p2, float(rng.uniform(0.006, 0.03)), p))
+    budget = {(k, c): 1.0 for k in range(ns) for c in range(ncomp)}
+    n_uni = {k: 0 for k in range(ns)}
+    for _ in range(int(rng.integers(1, 3 * ns))):
+        a = int(rng.integers(0, ns))
+        if n_uni[a] >= 4:
+            continue
+        kinds = [W.KEEP, W.SPLIT, W.EMIT] + ([W.TRANSLOCATE] if ncomp == 2 else [])
+        placement = kinds[int(rng.integers(0, len(kinds)))]
+        frm = int(rng.integers(0, ncomp)) if (placement == W.TRANSLOCATE or rng.random() < 0.3) \
+            and ncomp == 2 else -1
+        comps = range(ncomp) if frm < 0 else [frm]
+        p = float(rng.uniform(0.002, 0.05))
+        if any(budget[(a, c)] < p for c in comps):
+            continue
+        for c in comps:
+            budget[(a, c)] -= p
+        release = float(rng.uniform(0.002, 0.06))
+        if placement == W.KEEP:
+            rules.append(W.unimol(a, int(rng.integers(-1, ns)), p))
+        elif placement == W.TRANSLOCATE:
+            rules.append(W.unimol(a, int(rng.integers(-1, ns)), p, placement=W.TRANSLOCATE,
+                                  release=release, from_comp=frm, to_comp=1 - frm))
+        else:
+            p1 = int(rng.integers(0, ns)) if placement == W.SPLIT else int(rng.integers(-1, ns))
+            rules.append(W.unimol(a, p1, p, placement=placement, p2=int(rng.integers(0, ns)),
+                                  release=release, from_comp=frm))
+        n_uni[a] += 1
+    # dense: about 4,000 agents per cubic micrometre
+    vol = n / 4000.0
+    kw = {}
+    if geometry == W.PERIODIC_BOX:
+        kw["box_um"] = float(max(vol ** (1 / 3), 0.2))
+    else:
+        r = float(max((vol * 3 / (4 * np.pi)) ** (1 / 3), 0.15))
+        kw["outer_radius_um"] = r
+        if geometry == W.NESTED_SPHERES:
+            kw["inner_radius_um"] = 0.6 * r
+    return W.Model(f"fuzz{seed}", geometry, 1e-6, seed, species, rules, capacity=4 * n + 4096,
+                   **kw)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_models_match_oracle(seed):
+    m = random_model(seed)
+    run_pair(m, [1, 2, 5, 12, 25])
+
+
+@pytest.mark.parametrize("seed", [100, 101, 102])
+def test_random_models_binning_every_step(seed):
+    import paper_2606_14603_amd as mabm
+    m = random_model(seed)
+    g, _ = run_pair(m, [1, 7, 20])
+    h = mabm.Sim(m, record=True, cell_um=0.0)
+    h.set_param(mabm.PARAM_BIN_EVERY_MAX, 1)
+    h.step(20)
+    a, b = g.export(), h.export()
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint32) if a[k].dtype == np.float32 else a[k],
+                              b[k].view(np.uint32) if b[k].dtype == np.float32 else b[k]), k
+
+
+@pytest.mark.parametrize("seed", range(200, 210))
+def test_random_model_batches_match_oracle(seed):
+    # one random model, five simulations of it with their own seeds, volumes
+    # and initial counts (one of them empty), stepped as one batch
+    from test_gpu_batch import run_batch
+    base = random_model(seed)
+    rng = np.random.default_rng(seed + 1)
+    models = []
+    for k in range(5):
+        scale = 0.0 if k == 3 else float(rng.uniform(0.3, 1.5))
+        species = [W.Species(s.name, s.diffusion_um2_s, int(s.count * scale), s.compartment)
+                   for s in base.species]
+        f = max(scale, 0.3) ** (1 / 3)
+        kw = ({"box_um": base.box_um * f} if base.geometry == W.PERIODIC_BOX else
+              {"outer_radius_um": base.outer_radius_um * f,
+               "inner_radius_um": base.inner_radius_um * f})
+        n = sum(s.count for s in species)
+        models.append(base.with_(name=f"{base.name}_{k}", seed=seed * 10 + k, species=species,
+                                 capacity=4 * n + 4096, **kw))
+    run_batch(models, [1, 3, 10, 20])
