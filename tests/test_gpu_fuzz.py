@@ -129,3 +129,44 @@ def test_random_model_batches_match_oracle(seed):
         models.append(base.with_(name=f"{base.name}_{k}", seed=seed * 10 + k, species=species,
                                  capacity=4 * n + 4096, **kw))
     run_batch(models, [1, 3, 10, 20])
+
+
+def scaled(m: W.Model, n: int) -> W.Model:
+    """m with about n agents at the same density, its splits and emissions
+    five times rarer (births stay within a step's limit and the capacity)."""
+    from dataclasses import replace
+    rules = [r if r.kind == W.BIMOL or r.placement in (W.KEEP, W.TRANSLOCATE)
+             else replace(r, prob_per_step=r.prob_per_step / 5) for r in m.rules]
+    m = m.with_(rules=rules)
+    f = n / max(m.n_agents, 1)
+    species = [W.Species(s.name, s.diffusion_um2_s, int(round(s.count * f)), s.compartment)
+               for s in m.species]
+    g = f ** (1 / 3)
+    kw = ({"box_um": m.box_um * g} if m.geometry == W.PERIODIC_BOX else
+          {"outer_radius_um": m.outer_radius_um * g, "inner_radius_um": m.inner_radius_um * g})
+    total = sum(s.count for s in species)
+    return m.with_(species=species, capacity=4 * total + 4096, **kw)
+
+
+@pytest.mark.parametrize("seed", range(300, 310))
+def test_random_larger_models_and_launch_shapes(seed):
+    # 20k-60k agents (many chunks, scan tiles and a ragged tail), a random
+    # cell size, launch shape and graph replay: results stay the oracle's
+    import oracle
+    import paper_2606_14603_amd as mabm
+    from parity import assert_same
+    rng = np.random.default_rng(seed)
+    m = scaled(random_model(seed), int(rng.integers(20_000, 60_000)))
+    rmax = max([r.radius_um for r in m.rules if r.kind == W.BIMOL] + [0.006])
+    cell = 0.0 if rng.random() < 0.3 else float(rmax * rng.uniform(1.05, 4.0))
+    g = mabm.Sim(m, record=True, cell_um=cell, graphs=bool(rng.random() < 0.5))
+    g.set_param(mabm.PARAM_PROPOSE_LANES, int(rng.choice([0, 8, 16])))
+    g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, int(rng.choice([0, 256, 4096])))
+    G, _ = g.grid()
+    o = oracle.OracleSim(m, grid_n=G)
+    done = 0
+    for c in (1, 4, 17, 40):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        assert_same(g.export(), o.export(), f"{m.name} t={c} G={G}")
