@@ -161,6 +161,7 @@ class Sim:
         if rc != OK:
             raise MabmError(rc, L.mabm_last_error(None).decode())
         self._h = h
+        self._lib = L
         self._add_model(model)
 
     def _add_model(self, model):
@@ -183,7 +184,9 @@ class Sim:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().mabm_destroy_sim(self._h)
+            # the library handle is held by the object, so that a simulation
+            # collected at interpreter exit can still be destroyed
+            self._lib.mabm_destroy_sim(self._h)
             self._h = None
 
     def __del__(self):
@@ -337,6 +340,7 @@ class Batch(Sim):
         if rc != OK:
             raise MabmError(rc, L.mabm_last_error(None).decode())
         self._h = h
+        self._lib = L
         self._add_model(m0)
         for k in range(self.n_species):
             c = np.array([int(m.species[k].count) for m in models], np.uint32)
