@@ -78,9 +78,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # 512 MiB device copy in that run (FETCH x2.0, WRITE x1.0).  Valid only for
 # the kernel sources it was taken on (SHA-256 of the three files below).
 TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "79820a51a5c7a53bac57be995a58115a5a934a337b8c2a59434360d78a2da6e9",
+           "sources_sha256": "42097d79359f869332d6888b7d7987146581af4f1135c3104f43067129259ec6",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19628.3, 40070.4), "scan": (4631.8, 16416.1), "scatter": (34493.4, 56192.5), "propose": (17822.3, 2952.0), "finish": (152.5, 0.5)}}
+           "kib": {"move": (19629.7, 40071.2), "scan": (4631.8, 16416.1), "scatter": (34501.1, 56197.2), "propose": (17828.8, 2951.4), "finish": (152.5, 0.5)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
