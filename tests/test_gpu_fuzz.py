@@ -170,3 +170,37 @@ def test_random_larger_models_and_launch_shapes(seed):
         o.step(c - done)
         done = c
         assert_same(g.export(), o.export(), f"{m.name} t={c} G={G}")
+
+
+@pytest.mark.parametrize("seed", range(400, 406))
+def test_checkpoint_resume_continues_the_trajectory(seed):
+    # export a random model's state mid-run, import it into a fresh
+    # simulation at the same step, and run both on: identical to the
+    # uninterrupted run, and to the oracle
+    import oracle
+    import paper_2606_14603_amd as mabm
+    from parity import assert_same
+    m = random_model(seed)
+    g = mabm.Sim(m, record=True)
+    G, _ = g.grid()
+    o = oracle.OracleSim(m, grid_n=G)
+    g.step(13)
+    o.step(13)
+    e = g.export()
+    n, next_id = g.size()
+    _, t = g.counts()
+    assert t == 13
+    h = mabm.Sim(m, record=True)
+    h.import_state(e["id"], e["species"], e["x"], e["y"], e["z"], next_id, t)
+    assert h.grid()[0] == G
+    done = 0
+    for c in (1, 5, 12):
+        for sim in (g, h, o):
+            sim.step(c - done)
+        done = c
+        a, b = g.export(), h.export()
+        for f in ("id", "species", "x", "y", "z", "key"):
+            assert np.array_equal(a[f].view(np.uint32) if a[f].dtype == np.float32 else a[f],
+                                  b[f].view(np.uint32) if b[f].dtype == np.float32 else b[f]), f
+        assert_same(a, o.export(), f"{m.name} t={13 + c}")
+        assert h.counts()[1] == 13 + c
