@@ -311,7 +311,7 @@ def main() -> int:
                          "counter profile of this command holds a copy kernel of known bytes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
 
