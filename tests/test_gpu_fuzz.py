@@ -24,11 +24,11 @@ def _gpu():
     mabm.lib()
 
 
-def random_model(seed: int) -> W.Model:
+def random_model(seed: int, ns: int = 0, bimol_tries: int = 0, unimol_tries: int = 0) -> W.Model:
     rng = np.random.default_rng(seed)
     geometry = [W.PERIODIC_BOX, W.SPHERE, W.NESTED_SPHERES][seed % 3]
     ncomp = 2 if geometry == W.NESTED_SPHERES else 1
-    ns = int(rng.integers(3, 13))
+    ns = ns or int(rng.integers(3, 13))
     n = int(rng.integers(1500, 4000))
     counts = rng.multinomial(n, rng.dirichlet(np.ones(ns)))
     species = []
@@ -37,7 +37,7 @@ def random_model(seed: int) -> W.Model:
         species.append(W.Species(f"s{k}", d, int(counts[k]), int(rng.integers(0, ncomp))))
     rules = []
     pairs = set()
-    for _ in range(int(rng.integers(1, 2 * ns))):
+    for _ in range(bimol_tries or int(rng.integers(1, 2 * ns))):
         a, b = (int(v) for v in rng.integers(0, ns, 2))
         if rng.random() < 0.15:
             b = a
@@ -50,7 +50,9 @@ def random_model(seed: int) -> W.Model:
         rules.append(W.bimol(a, b, p1, p2, float(rng.uniform(0.006, 0.03)), p))
     budget = {(k, c): 1.0 for k in range(ns) for c in range(ncomp)}
     n_uni = {k: 0 for k in range(ns)}
-    for _ in range(int(rng.integers(1, 3 * ns))):
+    for _ in range(unimol_tries or int(rng.integers(1, 3 * ns))):
+        if len(rules) >= 255:
+            break
         a = int(rng.integers(0, ns))
         if n_uni[a] >= 4:
             continue
@@ -204,3 +206,11 @@ def test_checkpoint_resume_continues_the_trajectory(seed):
                                   b[f].view(np.uint32) if b[f].dtype == np.float32 else b[f]), f
         assert_same(a, o.export(), f"{m.name} t={13 + c}")
         assert h.counts()[1] == 13 + c
+
+
+@pytest.mark.parametrize("seed", range(500, 506))
+def test_random_models_at_the_table_limits(seed):
+    # 64 species and up to 255 rules (pair rules with indices above 127)
+    m = random_model(seed, ns=64, bimol_tries=170, unimol_tries=400)
+    assert len(m.species) == 64 and len(m.rules) > 200
+    run_pair(m, [1, 3, 10, 20])
