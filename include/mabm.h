@@ -8,9 +8,10 @@
  * displacement, finds reaction partners by spatial proximity, fires binding,
  * catalysis, unbinding, translocation, emission and degradation rules, and
  * compacts births and deaths.  The exact step definition (random-number
- * layout, boundaries, claim rule, placement of products) is the one written
- * out in the design notes as O0..O10; every call below names the paper
- * passage whose input or output it carries.
+ * layout, boundaries, claim rule, placement of products) is fixed in phases
+ * O0..O10, the same for this library and for the oracle its tests compare
+ * it with; every call below names the paper passage whose input or output
+ * it carries.
  *
  * Conventions for every call:
  *   - Return value: mabm_status, 0 = MABM_OK, negative = error.  No call

@@ -5,7 +5,8 @@ CPU-baseline leg of ``bench.py`` may import this package; the product path
 (``paper_2606_14603_amd``) never does, and this package never imports it.
 
 The oracle computes the molecule-agent step of the paper (Abstract; Sec. 2)
-under the step definition O0..O10 of the design notes, literally and slowly.
+under the step definition O0..O10 (stated phase by phase in mabm_oracle.c),
+literally and slowly.
 """
 from __future__ import annotations
 

@@ -13,8 +13,9 @@
  * products (Abstract), migrate between compartments (Abstract; Sec. 3.4) and
  * are emitted by expressor agents (Sec. 2, functional classes) or degraded
  * (Sec. 3.4).  The paper defers the exact stepping rules to earlier work, so
- * the step is fixed by the readings O0..O10 of the design notes; the
- * comment of each function names the step it follows.
+ * the step is fixed by a definition in phases O0..O10; the comment of each
+ * function states the phase it follows and the reading it takes where the
+ * paper is silent.
  *
  * Parity pins: Philox against rocRAND's host implementation; log/sin/cos
  * against numpy float64; neighbour search against the O(N^2) mode; the

@@ -12,8 +12,9 @@
  * molecule is an agent that diffuses in 3D, binds partners found by spatial
  * proximity, releases products, crosses compartments, is emitted by
  * expressors and degrades.  The paper leaves the stepping rules to earlier
- * work, so every rule below is the reading written out in the design notes
- * (step definition O0..O10); each function names the step it implements.
+ * work, so every rule below is a reading of the paper, written out phase by
+ * phase (O0..O10) in mabm_oracle.c; each function names the phase it
+ * implements.
  *
  * All floating point is IEEE binary32, evaluated left to right exactly as
  * written, built with -ffp-contract=off.
