@@ -214,3 +214,43 @@ def test_random_models_at_the_table_limits(seed):
     m = random_model(seed, ns=64, bimol_tries=170, unimol_tries=400)
     assert len(m.species) == 64 and len(m.rules) > 200
     run_pair(m, [1, 3, 10, 20])
+
+
+@pytest.mark.parametrize("seed", [600, 601, 602])
+def test_random_batch_counts_ring(seed):
+    # the device counts ring of a batch of random models, against the
+    # oracle's counts of each simulation run alone
+    import oracle
+    import paper_2606_14603_amd as mabm
+    base = random_model(seed)
+    models = [base.with_(name=f"{base.name}_{k}", seed=seed * 10 + k) for k in range(3)]
+    b = mabm.Batch(models, graphs=True)
+    b.record_counts(4, entries=64)
+    b.step(9)
+    b.step(15)
+    steps, counts = b.ring()
+    assert list(steps) == [4, 8, 12, 16, 20, 24]
+    for k, m in enumerate(models):
+        o = oracle.OracleSim(m)
+        for e, st in enumerate(steps):
+            o.step(int(st) - (int(steps[e - 1]) if e else 0))
+            want, t = o.counts()
+            assert t == st
+            assert np.array_equal(counts[e, k, :len(m.species)], want), (k, st)
+
+
+def test_random_models_served_concurrently():
+    # requests of different random models served concurrently on streams
+    # of their own: each result equals the oracle's counts for it alone
+    import oracle
+    from paper_2606_14603_amd import serve
+    models = [random_model(700 + k).with_(steps=30 + 7 * k) for k in range(6)]
+    want = {}
+    for m in models:
+        o = oracle.OracleSim(m)
+        o.step(m.steps)
+        want[m.name] = o.counts()[0]
+    res = serve.Server(1 << 34, max_active=4, chunk=16).run(models, np.zeros(len(models)))
+    assert sorted(r.name for r in res) == sorted(want)
+    for r in res:
+        assert np.array_equal(r.counts, want[r.name]), r.name
