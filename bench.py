@@ -156,11 +156,21 @@ def _bits(e: dict) -> dict:
 
 def run_sweep(args, torch, mabm, W) -> dict:
     """The dose x replicate sweep: every simulation for its whole horizon,
-    once as one batch and once one at a time through the single-simulation
-    path (a sample of simulations, extrapolated), with the sampled
-    simulations' final states compared bit for bit."""
+    once as one batch (its cell density and launch shape chosen by the
+    batch tuner beforehand, unless --no-tune) and once one at a time
+    through the single-simulation path (a sample of simulations at their
+    default grids, extrapolated), with the sampled simulations' final states
+    compared bit for bit."""
     models = W.c4_sweep(n_reps=args.sweep_reps, steps=args.sweep_steps)
     n, steps = len(models), args.sweep_steps
+    tuned, serial_models = None, models
+    if not args.no_tune:
+        # the batch's cell density and launch shape, timed on the batch
+        # itself (results do not depend on them); the serial sample keeps
+        # each simulation's default grid, the faster one for a lone run
+        from paper_2606_14603_amd import tune
+        tuned = tune.tune_batch(models)
+        models = tuned.models(models)
     agents = sum(m.n_agents for m in models)
     # warm the code objects on a small batch first
     warm = mabm.Batch(models[:2])
@@ -169,6 +179,8 @@ def run_sweep(args, torch, mabm, W) -> dict:
     del warm
     # each step of the batch is replayed from a captured graph
     batch = mabm.Batch(models, graphs=True)
+    if tuned is not None:
+        tuned.apply(batch)
     batch.grid()  # finalize: tables, placement
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -183,7 +195,7 @@ def run_sweep(args, torch, mabm, W) -> dict:
     sample = list(range(0, n, max(1, n // args.sweep_sample)))[:args.sweep_sample]
     ms_serial, same = 0.0, True
     for k in sample:
-        sim = mabm.Sim(models[k], graphs=True)
+        sim = mabm.Sim(serial_models[k], graphs=True)
         sim.grid()
         torch.cuda.synchronize()
         a = torch.cuda.Event(enable_timing=True)
@@ -206,7 +218,11 @@ def run_sweep(args, torch, mabm, W) -> dict:
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"c4_sweep: {len(models) // args.sweep_reps} doses x "
                                f"{args.sweep_reps} replicates of c2_mapk, 20k-200k agents each, "
-                               f"{steps} steps", "sims": n, "agents": agents},
+                               f"{steps} steps", "sims": n, "agents": agents,
+                   "tuned": None if tuned is None else {
+                       "agents_per_cell": tuned.agents_per_cell, "lanes": tuned.lanes,
+                       "min_workgroups": tuned.min_workgroups,
+                       "ms_per_step": {k: round(v, 4) for k, v in tuned.ms_per_step.items()}}},
         "batched": {"ms": ms_batch, "agent_updates_per_s": updates / (ms_batch * 1e-3)},
         "serial": {"value": serial, "unit": "sims/s", "ms_extrapolated": ms_serial_all,
                    "sample": f"{len(sample)} of {n} simulations run one at a time, "
@@ -283,7 +299,10 @@ def main() -> int:
     ap.add_argument("--cell-um", type=float, default=0.0,
                     help="spatial-hash cell size (0: the library's choice)")
     ap.add_argument("--tune", action="store_true",
-                    help="time candidate cell sizes first and run with the fastest")
+                    help="c2/c1/c3: time candidate cell sizes first and run with the fastest")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c4: skip the batch tuner (cell density, launch shape) and use the "
+                         "default grids")
     ap.add_argument("--workload", choices=("c1", "c2", "c3", "c4", "c5"), default="c2",
                     help="c2: the 2M-agent cascade step (agent-updates/s, the headline); "
                          "c1: A+B<->C, 20k agents in a periodic box; c3: nested "

@@ -1,4 +1,5 @@
-"""Cell-size autotuner.
+"""Cell-size and launch-shape autotuner, for one simulation (tune_cell) and
+for a batch (tune_batch).
 
 The spatial hash's cell size h is a pure performance choice: the step's
 results do not depend on it (only the exported cell ids do).  Coarse cells
@@ -142,3 +143,67 @@ def tune_cell(model, steps: int = 20, warm: int = 5, cache_path: Optional[str] =
         with open(cache_path, "w") as f:
             json.dump(_CACHE, f, indent=1, sort_keys=True)
     return TuneResult(best, timings, False, lanes, minwg, per_shape)
+
+
+@dataclass
+class BatchTuneResult:
+    agents_per_cell: float      # 0: the library's default grid for every simulation
+    lanes: int = 0
+    min_workgroups: int = 0
+    ms_per_step: Dict[str, float] = field(default_factory=dict)
+
+    def models(self, models):
+        """``models`` with the tuned cell size set on each."""
+        return [m.with_(cell_um=batch_cell(m, self.agents_per_cell)) for m in models]
+
+    def apply(self, batch) -> None:
+        from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+        batch.set_param(PARAM_PROPOSE_LANES, self.lanes)
+        batch.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, self.min_workgroups)
+
+
+def batch_cell(m, agents_per_cell: float) -> float:
+    """Cell size giving about ``agents_per_cell`` agents per cell over the
+    simulation's volume (0: the library's default), kept at or above the
+    largest contact radius and within the 512-cell grid."""
+    if agents_per_cell <= 0 or m.n_agents == 0:
+        return 0.0
+    h = (_volume(m) * agents_per_cell / m.n_agents) ** (1.0 / 3.0)
+    h = max(h, 1.01 * _rmax(m), _extent(m) / 512.0)
+    return h * (1.0 + 1e-6)
+
+
+def _time_batch(models, agents_per_cell: float, shape: Tuple[int, int], steps: int,
+                warm: int) -> float:
+    import torch
+    from . import Batch, PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+    b = Batch([m.with_(cell_um=batch_cell(m, agents_per_cell)) for m in models], graphs=True)
+    b.set_param(PARAM_PROPOSE_LANES, shape[0])
+    b.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, shape[1])
+    b.step(warm)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    b.close()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_batch(models, steps: int = 32, warm: int = 16) -> BatchTuneResult:
+    """Cell density and neighbour-search launch shape for a batch, timed on
+    the batch itself: every simulation at about 0.5, 1, 2, 4 or 8 agents
+    per cell, or at the library's default grids, then the launch shapes of
+    ``shapes`` at the fastest.  Results do not depend on either."""
+    timings = {a: _time_batch(models, a, (0, 0), steps, warm)
+               for a in (0.0, 0.5, 1.0, 2.0, 4.0, 8.0)}
+    best = min(timings, key=timings.get)
+    per = {f"cells:{a}": t for a, t in timings.items()}
+    shape_t = {(0, 0): timings[best]}
+    for sh in [(8, 0), (0, 512), (0, 8192)]:
+        shape_t[sh] = _time_batch(models, best, sh, steps, warm)
+        per[f"shape:{sh[0]},{sh[1]}"] = shape_t[sh]
+    lanes, minwg = min(shape_t, key=shape_t.get)
+    return BatchTuneResult(best, lanes, minwg, per)
