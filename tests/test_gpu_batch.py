@@ -128,3 +128,28 @@ def test_many_tiny_simulations_share_waves():
         m.seed = 1000 + k
         models.append(m)
     run_batch(models, [1, 2, 5, 20, 60])
+
+
+def test_batch_tuner_choice_changes_no_result():
+    # the batch tuner's cell density and launch shape: the tuned batch's
+    # states equal the default batch's bit for bit
+    import paper_2606_14603_amd as mabm
+    from paper_2606_14603_amd import tune
+    models = [W.c2(n, seed=70 + k, steps=12) for k, n in enumerate((20_000, 45_000, 8_000))]
+    for k, m in enumerate(models):
+        m.name = f"c2_tuned{k}"
+    tr = tune.tune_batch(models, steps=4, warm=2)
+    say(f"[batch] tuned: {tr.agents_per_cell} agents per cell, lanes {tr.lanes}, "
+        f"workgroups {tr.min_workgroups}")
+    a = mabm.Batch(tr.models(models), record=True)
+    tr.apply(a)
+    b = mabm.Batch(models, record=True)
+    a.step(12)
+    b.step(12)
+    for k in range(len(models)):
+        ea, eb = a.export(k), b.export(k)
+        for f in ("id", "species", "x", "y", "z", "event", "partner"):
+            x, y = ea[f], eb[f]
+            if x.dtype == np.float32:
+                x, y = x.view(np.uint32), y.view(np.uint32)
+            assert np.array_equal(x, y), (k, f)
