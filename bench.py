@@ -10,6 +10,12 @@ Prints one JSON line with the metric, the dominant kernel's roofline (kernel
 durations from HIP events that each kernel's dispatch stamps at its start and
 end, on the simulation's stream) and the CPU oracle's rate on a bounded
 sample of the same workload.
+
+Other workloads (--workload): c1 and c3 (agent-updates/s of the reversible
+binding box and of the nested-compartment model), c4 (the dose x replicate
+sweep as one tuned batch: simulations/s against one at a time, states
+compared bit for bit), c5 (the serving loop: p50/p99 latency and requests/s,
+concurrent against FIFO).
 """
 from __future__ import annotations
 
