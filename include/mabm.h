@@ -10,8 +10,9 @@
  * compacts births and deaths.  The exact step definition (random-number
  * layout, boundaries, claim rule, placement of products) is fixed in phases
  * O0..O10, the same for this library and for the oracle its tests compare
- * it with; every call below names the paper passage whose input or output
- * it carries.
+ * it with.  Every call below names the paper passage whose input or output
+ * it carries; the calls that are infrastructure of a C library (freeing a
+ * handle, error messages, timing, launch parameters) say "no passage".
  *
  * Conventions for every call:
  *   - Return value: mabm_status, 0 = MABM_OK, negative = error.  No call
@@ -120,11 +121,17 @@ typedef struct {
 
 /* Device bytes a simulation with this configuration needs (an upper bound
  * independent of the model's species and rules beyond the stated counts).
- * Used for admission by HBM footprint.  Returns 0 for an invalid config. */
+ * Passage: Sec. 3.2 -- the multiple-seed runs were throughput-bound, many
+ * seeds sharing one GPU; the footprint is what a scheduler admits such runs
+ * by.  Returns 0 for an invalid config. */
 size_t mabm_arena_bytes(const mabm_config* cfg, uint32_t n_species, uint32_t n_rules);
 
 /* Create a simulation in the caller's device arena, working on the caller's
- * HIP stream (a hipStream_t, NULL = the null stream).  The arena is carved,
+ * HIP stream (a hipStream_t, NULL = the null stream).  Passage: Sec. 2,
+ * footnote on the key parameters -- the simulation volume and, for models
+ * with compartments, the compartments (here the geometry and its radii);
+ * the seed keys the random draws (Sec. 3.3 reports runs over several
+ * seeds).  The arena is carved,
  * not cleared beyond what the library needs.  *out receives an opaque handle
  * owned by the caller (free with mabm_destroy_sim).
  * Errors: E_INVALID (config), E_NOMEM (arena_bytes too small), E_DEVICE. */
@@ -144,7 +151,8 @@ mabm_status mabm_add_species(mabm_sim* sim, const char* name, float diffusion_um
  * E_INVALID).  Ids 0, 1, ... in call order. */
 mabm_status mabm_add_rule(mabm_sim* sim, const mabm_rule* rule, int32_t* out_rule_id);
 
-/* Cells per axis and cell size the simulation uses (after finalize). */
+/* Cells per axis and cell size the simulation uses (after finalize).  No
+ * passage: the spatial hash is this library's own device. */
 mabm_status mabm_grid(mabm_sim* sim, uint32_t* cells_per_axis, float* cell_um);
 
 /* Enqueue n_steps steps on the stream; returns without synchronising.  The
@@ -158,10 +166,14 @@ mabm_status mabm_step(mabm_sim* sim, uint32_t n_steps);
  * counter.  Synchronises the stream; reports sticky device errors. */
 mabm_status mabm_counts(mabm_sim* sim, uint64_t* out, uint32_t n_species, uint64_t* out_step);
 
-/* Number of live agents and the next id to be assigned (synchronises). */
+/* Number of live agents and the next id to be assigned (synchronises).
+ * Passage: Sec. 2, each molecule is an agent; the live count is the
+ * population the concentrations of Sec. 2 are taken over. */
 mabm_status mabm_size(mabm_sim* sim, uint32_t* n_live, uint32_t* next_id);
 
 /* Copy the live agents to host arrays of capacity >= n_live, sorted by id.
+ * Passage: Sec. 2, the three-dimensional viewer of the agents' spatial
+ * dynamics -- this is the state such a view (or a checkpoint) reads.
  * key: cell id cx + G (cy + G cz) of the moved position in the last step;
  * event: unimolecular rule fired in the last step (-1 none); partner: id of
  * the confirmed partner in the last step (MABM_NONE none).  key, event and
@@ -171,7 +183,10 @@ mabm_status mabm_export(mabm_sim* sim, uint32_t capacity, uint32_t* id, uint8_t*
                         float* x, float* y, float* z, uint32_t* key, int32_t* event,
                         uint32_t* partner);
 
-/* Replace the initial placement (or resume a checkpoint): n agents with the
+/* Passage: Sec. 2, per-species localisation and initial concentrations
+ * given by the user instead of the library's uniform placement (and Sec.
+ * 3.2's long runs, resumed from a checkpoint).
+ * Replace the initial placement (or resume a checkpoint): n agents with the
  * given ids (distinct, all < next_id), species and positions (inside the
  * volume), and the step counter t.  E_INVALID for a null array (n > 0), an
  * unknown species, a repeated id, an id not below next_id or a position
@@ -247,7 +262,11 @@ mabm_status mabm_batch_grid(mabm_sim* sim, uint32_t sim_index, uint32_t* cells_p
  * is switched off with every = 0); a full ring overwrites its oldest entry.
  * An entry is uint64 words: the step counter, then for every simulation of
  * the handle (one unless it is a batch) MABM_MAX_SPECIES species counts.
- * Recording splits graph replays at entry steps; results do not change. */
+ * Recording splits graph replays at entry steps; results do not change.
+ * Replacing a ring, or switching it off, first synchronises the stream, so
+ * the old buffer may be freed (or reused) as soon as the call returns; the
+ * new buffer must be ready (e.g. zero-filled) before the stream's next
+ * step, i.e. filled on that stream or on one it waits for. */
 size_t mabm_ring_entry_bytes(const mabm_sim* sim);
 mabm_status mabm_counts_ring(mabm_sim* sim, void* device_ring, uint32_t entries, uint32_t every);
 
@@ -258,7 +277,8 @@ mabm_status mabm_counts_ring(mabm_sim* sim, void* device_ring, uint32_t entries,
 mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
                            uint64_t* n_recorded);
 
-/* Launch-shape parameters of the neighbour search, for tuning (results do
+/* No passage (tuning of this library's kernels).
+ * Launch-shape parameters of the neighbour search, for tuning (results do
  * not depend on them).  MABM_PARAM_PROPOSE_LANES: lanes per claimer, 4, 8,
  * 16 or 32 (0: the library's choice; raised to the least that covers the
  * stencil with two cells per lane).  MABM_PARAM_PROPOSE_MIN_WORKGROUPS: the
@@ -282,7 +302,8 @@ mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
 mabm_status mabm_set_param(mabm_sim* sim, int32_t param, uint32_t value);
 mabm_status mabm_get_param(mabm_sim* sim, int32_t param, uint32_t* value);
 
-/* Per-kernel timing: while enabled (1), each step kernel is dispatched with
+/* No passage (measurement of this library's kernels).
+ * Per-kernel timing: while enabled (1), each step kernel is dispatched with
  * a pair of HIP events that the dispatch itself stamps at the kernel's start
  * and end, so the time is the kernel's own duration; steps then run as
  * direct launches, somewhat slower than untimed ones.  Disable with 0.  read
@@ -295,14 +316,32 @@ mabm_status mabm_profile_read(mabm_sim* sim, const char** names, uint64_t* launc
                               double* total_ms);
 
 /* Sum over all steps so far of the live agents at the start of each step
- * (the agent-update count).  Synchronises. */
+ * (the agent-update count).  Passage: Sec. 3.2, per-step cost scales with
+ * the agent count; this is that count summed over the steps run.
+ * Synchronises. */
 mabm_status mabm_agent_updates(mabm_sim* sim, uint64_t* out);
 
-/* Free the host handle (the arena and stream stay the caller's). */
+/* Digest of the current state, one per simulation of the handle (out has
+ * n = 1 entry, or n_sims for a batch): the sum mod 2^64 over the live agents
+ * of a 64-bit hash of (id, species, position bits), mixed by MurmurHash3's
+ * 64-bit finaliser as h = f(f(f((id << 32 | species) ^ 0x9E3779B97F4A7C15)
+ * ^ (x_bits << 32 | y_bits)) ^ z_bits).  It does not depend on where the
+ * agents sit in memory, so two runs that reach the same id-keyed state give
+ * the same digest, and a state that differs in any agent's id, species or
+ * position bits gives another one with overwhelming probability.  No
+ * passage (verification: checking that batched and served runs equal
+ * single runs without copying whole states to the host).  E_INVALID if n is
+ * not the handle's simulation count.  Synchronises. */
+mabm_status mabm_digest(mabm_sim* sim, uint64_t* out, uint32_t n);
+
+/* Free the host handle (the arena and stream stay the caller's).  No
+ * passage (C library infrastructure). */
 mabm_status mabm_destroy_sim(mabm_sim* sim);
 
 /* Message of the last failing call on sim (or of the last failed create
- * when sim is NULL).  Valid until the next call on sim. */
+ * when sim is NULL).  Valid until the next call on sim.  No passage (C
+ * library infrastructure); the messages of model errors name the
+ * consistency checks of Sec. 2. */
 const char* mabm_last_error(const mabm_sim* sim);
 
 #ifdef __cplusplus

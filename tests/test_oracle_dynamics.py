@@ -12,6 +12,7 @@ not exactly stationary, a wrong release placement) fails it:
   counts; the two-state Markov law of translocation; the release geometry of
   a split; the detailed-balance steady state of A + B <-> C.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -231,7 +232,16 @@ def test_mass_action_steady_state_detailed_balance():
     """A + B <-> C with release uniform in the R-ball: detailed balance fixes
     q E[N_C] = p (V_R / V) E[N_A N_B].  Start at the stationary composition
     with uniform positions and compare time-averaged N_C over 12 seeds with
-    the closed-form root, within 3 standard errors of the seed mean."""
+    the closed-form root, within 3 standard errors of the seed mean; the
+    measured flux ratio q N_C / (p (V_R / V) N_A N_B) likewise within 3
+    standard errors of 1.
+
+    Scaled setup (so that the CPU run takes seconds and relaxes within the
+    horizon): A + C = B + C = 2,000 agents in a periodic 1 um cube, contact
+    radius 10 nm with p = 0.5, unbinding q = 1e-2 per step (release ball
+    5 nm), 12 seeds x 1,500 steps sampled every 25.  The relaxation time
+    falls with q, so the reversible-binding workload's own q = 1e-3 would
+    need about ten times the horizon."""
     L, R, p, q, n0 = 1.0, 0.010, 0.5, 1e-2, 2000
     K_over_V = p * (4.0 / 3.0 * math.pi * R ** 3) / q / L ** 3
     nc_star = _solve_steady(n0, K_over_V)
@@ -251,6 +261,35 @@ def test_mass_action_steady_state_detailed_balance():
         flux.append(q * np.mean(ncs) / (K_over_V * q * np.mean(prods)))
     means = np.array(means)
     se = means.std(ddof=1) / math.sqrt(len(means))
-    assert abs(means.mean() - nc_star) <= 3 * se + 0.006 * nc_star, (means.mean(), nc_star, se)
+    assert abs(means.mean() - nc_star) <= 3 * se, (means.mean(), nc_star, se)
     fr = np.array(flux)
-    assert abs(fr.mean() - 1.0) <= 3 * fr.std(ddof=1) / math.sqrt(len(fr)) + 0.006
+    fse = fr.std(ddof=1) / math.sqrt(len(fr))
+    assert abs(fr.mean() - 1.0) <= 3 * fse, (fr.mean(), fse)
+
+
+def test_thread_count_changes_no_result():
+    """The oracle's move phase and neighbour search run on several threads;
+    children get ids in parent-id order and every other write is the
+    agent's own, so one thread and four give the same id-keyed state on a
+    model with births, deaths, splits, translocations and contact rules."""
+    m = W.c3(30_000, steps=60)
+    m = m.with_(rules=[r if r.prob_per_step >= 0.01 else dataclasses.replace(r, prob_per_step=r.prob_per_step * 50)
+                       for r in m.rules])
+    outs = []
+    before = oracle.threads()
+    try:
+        for nt in (1, 4):
+            assert oracle.threads(nt) == nt
+            s = oracle.OracleSim(m, grid_n=64)
+            s.step(60)
+            outs.append((s.export(), s.counts()))
+    finally:
+        oracle.threads(before)
+    (a, ca), (b, cb) = outs
+    assert np.array_equal(ca[0], cb[0]) and ca[1] == cb[1]
+    assert len(a["id"]) > m.n_agents  # births happened
+    for k in a:
+        x, y = a[k], b[k]
+        if x.dtype == np.float32:
+            x, y = x.view(np.uint32), y.view(np.uint32)
+        assert np.array_equal(x, y), k
