@@ -21,9 +21,10 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "mabm_oracle.c")
 
 # gcc flags: IEEE binary32 evaluated as written (no contraction, no
-# reassociation); plain -O2, no vector ISA beyond the x86-64 baseline.
+# reassociation); plain -O2, no vector ISA beyond the x86-64 baseline;
+# OpenMP for the two per-agent loops whose iterations are independent.
 CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-          "-Wall", "-Wextra"]
+          "-fopenmp", "-Wall", "-Wextra"]
 
 E_CODES = {0: "OK", -1: "E_INVALID", -2: "E_STATE", -3: "E_NOMEM", -4: "E_CAPACITY",
            -5: "E_DEVICE"}
@@ -71,6 +72,8 @@ def lib() -> ctypes.CDLL:
         L.orc_gauss3.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, P]
         L.orc_event_word.restype = c.c_uint32
         L.orc_event_word.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32]
+        L.orc_threads.restype = c.c_int
+        L.orc_threads.argtypes = [c.c_int]
         _lib = L
     return _lib
 
@@ -162,6 +165,12 @@ class OracleSim:
 
 
 # ---- building blocks, for the pin tests ----
+
+def threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel per-agent loops (n > 0 sets them);
+    returns the count the next step uses."""
+    return int(lib().orc_threads(int(n)))
+
 
 def philox(ctr, key) -> np.ndarray:
     c = np.ascontiguousarray(ctr, np.uint32)

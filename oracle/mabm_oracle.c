@@ -4,7 +4,12 @@
  * TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
  * CPU-baseline leg load this library.  It is deliberately slow and literal:
  * one loop per phase of the step definition, in the order the phases are
- * defined, no blocking, no fusion, no parallelism.
+ * defined, no blocking, no fusion.  The two per-agent loops whose
+ * iterations are independent (the move phase, where each agent writes only
+ * its own fields and appends at most one child, and the neighbour search of
+ * each claimer) are shared among OpenMP threads; children are ordered by
+ * parent id before they get ids, so no result depends on the thread count
+ * (a test compares 1 thread with several).
  *
  * Paper: the simulator of Maestri, "Towards In Silico Cancer Therapy Design"
  * (Abstract; Sec. 2).  Molecules are agents with physical properties that
@@ -25,6 +30,7 @@
 #include "mabm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -666,7 +672,10 @@ static void release_offset(const orc_sim* s, const rule_t* ru, uint32_t id, floa
 static void add_child(orc_sim* s, uint32_t parent, int sp, float x, float y, float z)
 {
     if (s->geometry == ORC_PERIODIC_BOX) { x = wrap1(s, x); y = wrap1(s, y); z = wrap1(s, z); }
-    child_t* k = &s->kids[s->nkids++];
+    uint32_t slot;
+#pragma omp atomic capture
+    slot = s->nkids++;
+    child_t* k = &s->kids[slot];
     k->parent = parent; k->sp = (uint8_t)sp; k->x = x; k->y = y; k->z = z;
 }
 
@@ -845,6 +854,7 @@ static int step_one(orc_sim* s)
 {
     uint32_t n = s->n;
     s->nkids = 0;
+#pragma omp parallel for schedule(static)
     for (uint32_t i = 0; i < n; ++i) phase_move(s, i);
 
     /* O6/O7: proposals */
@@ -854,6 +864,7 @@ static int step_one(orc_sim* s)
         s->prop_b[a] = -1;
         s->slot[a] = UINT64_MAX;
     }
+#pragma omp parallel for schedule(dynamic, 1024)
     for (uint32_t a = 0; a < n; ++a) {
         if (s->busy[a] || !s->is_claimer[s->sp[a]]) continue;
         int r = -1;
@@ -978,4 +989,12 @@ int orc_export(orc_sim* s, uint32_t cap, uint32_t* id, uint8_t* sp, float* x, fl
     }
     free(idx);
     return ORC_OK;
+}
+
+/* Threads of the two parallel loops (0: OpenMP's default); returns the
+ * number the next step will use. */
+int orc_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

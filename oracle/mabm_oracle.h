@@ -82,6 +82,9 @@ void  orc_sincos2pi(float a, float* s, float* c);
 void  orc_gauss3(uint64_t seed, uint32_t id, uint32_t t, float out[3]);
 /* the 32-bit unimolecular event draw of agent id at step t */
 uint32_t orc_event_word(uint64_t seed, uint32_t id, uint32_t t);
+/* threads of the parallel per-agent loops (n > 0 sets them); returns the
+ * count the next step uses */
+int orc_threads(int n);
 
 #ifdef __cplusplus
 }
