@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
         L.mabm_profile.argtypes = [P, c.c_int32]
         L.mabm_profile_read.argtypes = [P, P, P, P]
         L.mabm_agent_updates.argtypes = [P, P]
+        L.mabm_digest.argtypes = [P, P, c.c_uint32]
         L.mabm_destroy_sim.argtypes = [P]
         L.mabm_batch_arena_bytes.restype = c.c_size_t
         L.mabm_batch_arena_bytes.argtypes = [P, c.c_uint32, c.c_uint32, c.c_uint32]
@@ -102,7 +103,7 @@ def lib() -> ctypes.CDLL:
         L.mabm_last_error.argtypes = [P]
         for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
                      "mabm_step", "mabm_counts", "mabm_size", "mabm_export", "mabm_import",
-                     "mabm_profile", "mabm_profile_read", "mabm_agent_updates",
+                     "mabm_profile", "mabm_profile_read", "mabm_agent_updates", "mabm_digest",
                      "mabm_destroy_sim", "mabm_create_batch", "mabm_set_initial_counts",
                      "mabm_batch_counts", "mabm_batch_size", "mabm_batch_export",
                      "mabm_batch_grid", "mabm_counts_ring", "mabm_ring_read",
@@ -264,14 +265,23 @@ class Sim:
         import torch
         L = lib()
         if every <= 0:
+            # the library synchronises the simulation's stream before it lets
+            # go of the old ring, so the buffer is free once this returns
             self._chk(L.mabm_counts_ring(self._h, None, 0, 0))
             self._ring = None
             return
         words = int(L.mabm_ring_entry_bytes(self._h)) // 8
-        self._ring = torch.zeros(entries * words, dtype=torch.int64, device=self.arena.device)
-        self._ring_words, self._ring_entries = words, entries
-        self._chk(L.mabm_counts_ring(self._h, ctypes.c_void_p(self._ring.data_ptr()), entries,
+        dev = self.arena.device
+        ring = torch.zeros(entries * words, dtype=torch.int64, device=dev)
+        # the zero fill runs on the current stream: the simulation's stream,
+        # which writes the entries, waits for it, and the caching allocator
+        # is told that the buffer is in use on that stream
+        self.stream.wait_stream(torch.cuda.current_stream(dev))
+        ring.record_stream(self.stream)
+        self._chk(L.mabm_counts_ring(self._h, ctypes.c_void_p(ring.data_ptr()), entries,
                                      int(every)))
+        self._ring = ring
+        self._ring_words, self._ring_entries = words, entries
 
     def ring(self):
         """(steps, counts): the recorded entries, oldest first; counts has
@@ -288,6 +298,14 @@ class Sim:
         out = np.zeros(1, np.uint64)
         self._chk(lib().mabm_agent_updates(self._h, _ptr(out)))
         return int(out[0])
+
+    def digest(self) -> np.ndarray:
+        """Order-independent 64-bit digest of the id-keyed state, one per
+        simulation of the handle (uint64 array)."""
+        n = getattr(self, "n_sims", 1)
+        out = np.zeros(n, np.uint64)
+        self._chk(lib().mabm_digest(self._h, _ptr(out), n))
+        return out
 
 
 def _same_structure(a, b) -> bool:

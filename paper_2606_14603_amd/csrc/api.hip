@@ -82,7 +82,8 @@ bool config_ok(const mabm_config* c, std::string& why)
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
     size_t ctl, tab, rec[2], id[2], rank, event, sclaim, cell_count, cell_start, tile_acc, slot,
-        prop, plist, rkey, revent, rpartner, births, counts, next_id, head, nxt, glob, total;
+        prop, plist, rkey, revent, rpartner, births, counts, digest, next_id, head, nxt, glob,
+        total;
     uint32_t ncells, ntiles, tile_shift;
 };
 
@@ -131,6 +132,7 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.rpartner = take(cap * 4);
     L.births = take((size_t)kMaxBirthsPerStep * sizeof(Birth));
     L.counts = take((size_t)kMaxSpecies * 8 * n);
+    L.digest = take((size_t)8 * n);
     L.next_id = take((size_t)4 * n);
     L.head = take((padded + 1) * 4);
     L.nxt = take(cap * 4);
@@ -556,6 +558,7 @@ void fill_dev(mabm_sim* s)
     d.rpartner = (uint32_t*)(A + L.rpartner);
     d.births = (Birth*)(A + L.births);
     d.counts = (unsigned long long*)(A + L.counts);
+    d.digest = (unsigned long long*)(A + L.digest);
     d.next_id = (uint32_t*)(A + L.next_id);
     d.head = (uint32_t*)(A + L.head);
     d.nxt = (uint32_t*)(A + L.nxt);
@@ -1256,6 +1259,9 @@ mabm_status mabm_counts_ring(mabm_sim* s, void* device_ring, uint32_t entries, u
     if (!s) return MABM_E_INVALID;
     if (every && (!device_ring || entries == 0 || (uintptr_t)device_ring % 8 != 0))
         return fail(s, MABM_E_INVALID, "counts ring needs an 8-byte aligned buffer of >= 1 entry");
+    // steps already enqueued may still write the old ring: it is released
+    // only once they have run
+    if (s->ring) HIP_OK(s, hipStreamSynchronize(s->stream));
     s->ring = every ? (unsigned long long*)device_ring : nullptr;
     s->ring_entries = every ? entries : 0;
     s->ring_every = every;
@@ -1322,6 +1328,20 @@ mabm_status mabm_get_param(mabm_sim* s, int32_t param, uint32_t* value)
     }
     default: return fail(s, MABM_E_INVALID, "unknown parameter");
     }
+}
+
+mabm_status mabm_digest(mabm_sim* s, uint64_t* out, uint32_t n)
+{
+    if (!s || !out) return MABM_E_INVALID;
+    if (n != s->n_sims) return fail(s, MABM_E_INVALID, "digest array must have one entry per simulation");
+    mabm_status st = finalize(s, true);
+    if (st != MABM_OK) return st;
+    if (s->failed) return fail(s, MABM_E_STATE, "simulation has failed: " + s->err);
+    launch_digest(state_dev(s), s->parity, s->dev.digest, s->stream);
+    HIP_OK(s, hipGetLastError());
+    HIP_OK(s, hipMemcpyAsync(out, s->dev.digest, (size_t)8 * n, hipMemcpyDeviceToHost, s->stream));
+    Ctl ctl{};
+    return sync_ctl(s, &ctl);
 }
 
 mabm_status mabm_agent_updates(mabm_sim* s, uint64_t* out)
