@@ -168,6 +168,7 @@ struct Dev {
     uint32_t* rpartner;
     Birth* births;
     unsigned long long* counts;  // [n_sims][kMaxSpecies]
+    unsigned long long* digest;  // [n_sims], state digests (queries only)
     uint32_t* next_id;           // batch: per simulation, the next id to assign
     uint32_t* head;              // per cell: first agent of its extra chain (kEnd: none)
     uint32_t* nxt;               // per slot: next agent of its chain, kUnlinked, kGlobBit
@@ -214,5 +215,8 @@ void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, cons
 void launch_counts(const Dev& d, int cur, hipStream_t s, unsigned long long* dst = nullptr,
                    unsigned long long* tslot = nullptr);
 void launch_fill_records(const Dev& d, hipStream_t s);
+// per-simulation digests of the live agents (id, species, position bits)
+// into out[n_sims] (verification queries)
+void launch_digest(const Dev& d, int cur, unsigned long long* out, hipStream_t s);
 
 }  // namespace mabm

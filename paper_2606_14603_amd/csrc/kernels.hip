@@ -1223,6 +1223,75 @@ __global__ void __launch_bounds__(kBlock) k_counts_batch(Dev d, int cur)
     }
 }
 
+// State digest (verification only): each live agent contributes a 64-bit
+// hash of (id, species, position bits), mixed by the finaliser of Appleby's
+// MurmurHash3, and a simulation's digest is the sum of its agents' hashes
+// mod 2^64, so it does not depend on where the agents sit in the arrays.
+// Each wave walks a contiguous run of slots, sums its lanes per simulation
+// (agents are sorted by simulation, so a run meets few) and adds each
+// simulation's partial sum with one atomic when the simulation changes.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xFF51AFD7ED558CCDull;
+    k ^= k >> 33;
+    k *= 0xC4CEB9FE1A85EC53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ uint64_t agent_hash(uint32_t id, const uint4& r)
+{
+    uint64_t v = fmix64(((uint64_t(id) << 32) | (r.w & 0xFFu)) ^ 0x9E3779B97F4A7C15ull);
+    v = fmix64(v ^ ((uint64_t(r.x) << 32) | r.y));
+    return fmix64(v ^ uint64_t(r.z));
+}
+
+__global__ void __launch_bounds__(kBlock) k_digest(Dev d, int cur, unsigned long long* out,
+                                                   uint32_t per_wave)
+{
+    const uint32_t n = d.ctl->s[cur].n_slots;
+    const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const uint32_t lo = wave * per_wave;
+    const uint32_t hi = lo + per_wave < n ? lo + per_wave : n;
+    const Agents A = d.a[cur];
+    uint32_t acc_sim = kNone;  // wave-uniform
+    unsigned long long acc = 0;
+    for (uint32_t base = lo; base < hi; base += 64) {
+        const uint32_t i = base + uint32_t(lane_id());
+        uint32_t sim = kNone;
+        unsigned long long h = 0;
+        if (i < hi) {
+            const uint4 r = A.rec[i];
+            if ((r.w & 0xFFu) != kDead) {
+                sim = sim_of(r.w);
+                h = agent_hash(A.id[i], r);
+            }
+        }
+        // per simulation present in this round of lanes, in lane order
+        uint64_t left = __ballot(sim != kNone);
+        while (left) {
+            const uint32_t u = __shfl(sim, __builtin_ctzll(left), 64);
+            unsigned long long v = sim == u ? h : 0ull;
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (u != acc_sim) {
+                if (acc_sim != kNone && lane_id() == 0) atomicAdd(&out[acc_sim], acc);
+                acc_sim = u;
+                acc = 0;
+            }
+            acc += v;
+            left &= ~__ballot(sim == u);
+        }
+    }
+    if (acc_sim != kNone && lane_id() == 0) atomicAdd(&out[acc_sim], acc);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 // clears the counts; a counts-ring entry also gets the step counter
 __global__ void k_zero_counts(Dev d, int cur, unsigned long long* tslot)
 {
@@ -1298,6 +1367,17 @@ void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, cons
     if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record, bin);
     else go(k_finish<false>, nb, kBlock, s, ev, d, p, record, bin);
 }
+void launch_digest(const Dev& d, int cur, unsigned long long* out, hipStream_t s)
+{
+    k_zero_u64<<<blocks_for(d.n_sims), kBlock, 0, s>>>(out, d.n_sims);
+    // about 4,096 waves, each over a whole number of 64-slot rounds
+    const uint32_t waves = 4096;
+    uint32_t per_wave = (d.capacity + waves - 1) / waves;
+    per_wave = (per_wave + 63u) / 64u * 64u;
+    const uint32_t need = (d.capacity + per_wave - 1) / per_wave;  // waves that have slots
+    k_digest<<<(need + 3) / 4, kBlock, 0, s>>>(d, cur, out, per_wave);
+}
+
 void launch_counts(const Dev& d0, int cur, hipStream_t s, unsigned long long* dst,
                    unsigned long long* tslot)
 {

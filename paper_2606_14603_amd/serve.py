@@ -36,6 +36,9 @@ class Result:
     steps: int
     agents: int
     counts: np.ndarray = field(repr=False)
+    digest: int = 0        # order-independent digest of the final id-keyed state
+    grid: int = 0          # cells per axis the simulation ran on
+    state: Optional[dict] = field(default=None, repr=False)  # final export (keep_state)
 
     @property
     def latency_s(self) -> float:
@@ -52,10 +55,14 @@ class Server:
     simulations admitted at once (1 = FIFO, one request at a time);
     ``fill_agents``: admission stops while the admitted simulations hold at
     least this many agents, enough to fill the GPU (a large request then
-    runs nearly alone, as under FIFO, while small ones overlap)."""
+    runs nearly alone, as under FIFO, while small ones overlap).  Every
+    result carries the digest of its final state (``mabm_digest``);
+    ``keep_state`` also exports the state itself, id-keyed (with the last
+    step's cell ids, events and partners when ``record``)."""
 
     def __init__(self, budget_bytes: int, chunk: int = 256, max_active: int = 64,
-                 device: str = "cuda", progress=None, fill_agents: int = 1 << 62):
+                 device: str = "cuda", progress=None, fill_agents: int = 1 << 62,
+                 record: bool = False, keep_state: bool = False):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -64,6 +71,8 @@ class Server:
         self.device = device
         self.progress = progress  # called with each Result as it completes
         self.fill_agents = int(fill_agents)
+        self.record = bool(record)
+        self.keep_state = bool(keep_state)
         self._streams: List = []
 
     def _stream(self):
@@ -97,7 +106,7 @@ class Server:
                 queue.popleft()
                 a = _Active()
                 a.model, a.arrival, a.admitted = m, arr, time.perf_counter() - t0
-                a.sim = Sim(m, stream=self._stream(), graphs=True)
+                a.sim = Sim(m, stream=self._stream(), graphs=True, record=self.record)
                 a.left, a.event, a.bytes = int(m.steps), None, need
                 used += need
                 active.append(a)
@@ -108,9 +117,13 @@ class Server:
                 busy = True
                 if a.left == 0:
                     counts, _ = a.sim.counts()
-                    done.append(Result(a.model.name, a.arrival, a.admitted,
-                                       time.perf_counter() - t0, int(a.model.steps),
-                                       int(a.model.n_agents), counts))
+                    r = Result(a.model.name, a.arrival, a.admitted, time.perf_counter() - t0,
+                               int(a.model.steps), int(a.model.n_agents), counts,
+                               digest=int(a.sim.digest()[0]))
+                    if self.keep_state:
+                        r.grid = a.sim.grid()[0]
+                        r.state = a.sim.export()
+                    done.append(r)
                     if self.progress:
                         self.progress(done[-1])
                     self._streams.append(a.sim.stream)

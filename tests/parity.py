@@ -36,6 +36,29 @@ def assert_same(g: dict, o: dict, where: str):
     assert not msg, f"{where}: {msg}"
 
 
+def _fmix64(k: np.ndarray) -> np.ndarray:
+    # MurmurHash3's 64-bit finaliser (uint64 arithmetic wraps mod 2^64)
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xFF51AFD7ED558CCD)
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xC4CEB9FE1A85EC53)
+    return k ^ (k >> np.uint64(33))
+
+
+def state_digest(e: dict) -> int:
+    """The library's order-independent state digest (mabm_digest), computed
+    from an id-keyed export: the sum mod 2^64 over agents of
+    f(f(f((id << 32 | species) ^ c) ^ (x_bits << 32 | y_bits)) ^ z_bits)."""
+    u64 = np.uint64
+    ident = (e["id"].astype(u64) << u64(32)) | e["species"].astype(u64)
+    xb, yb, zb = (bits(e[k]).astype(u64) for k in "xyz")
+    with np.errstate(over="ignore"):
+        v = _fmix64(ident ^ u64(0x9E3779B97F4A7C15))
+        v = _fmix64(v ^ ((xb << u64(32)) | yb))
+        v = _fmix64(v ^ zb)
+        return int(v.sum(dtype=u64))
+
+
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()

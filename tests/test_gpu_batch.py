@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads as W
-from parity import assert_same, say
+from parity import assert_same, say, state_digest
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,12 @@ def run_batch(models, checkpoints, record=True):
         done = c
         counts, t = b.counts()
         assert t == c
+        digests = b.digest()
         for k, (m, o) in enumerate(zip(models, orcs)):
             ge, oe = b.export(k), o.export()
+            # the library's per-simulation state digest is that of the
+            # oracle's state
+            assert int(digests[k]) == state_digest(oe), (k, c)
             if not record:
                 for f in ("key", "event", "partner"):
                     ge.pop(f)

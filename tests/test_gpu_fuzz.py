@@ -241,16 +241,11 @@ def test_random_batch_counts_ring(seed):
 
 def test_random_models_served_concurrently():
     # requests of different random models served concurrently on streams
-    # of their own: each result equals the oracle's counts for it alone
-    import oracle
+    # of their own: each final state equals, agent by agent, the oracle's
+    # for the model run alone
     from paper_2606_14603_amd import serve
+    from test_gpu_serve import check_served
     models = [random_model(700 + k).with_(steps=30 + 7 * k) for k in range(6)]
-    want = {}
-    for m in models:
-        o = oracle.OracleSim(m)
-        o.step(m.steps)
-        want[m.name] = o.counts()[0]
-    res = serve.Server(1 << 34, max_active=4, chunk=16).run(models, np.zeros(len(models)))
-    assert sorted(r.name for r in res) == sorted(want)
-    for r in res:
-        assert np.array_equal(r.counts, want[r.name]), r.name
+    res = serve.Server(1 << 34, max_active=4, chunk=16, record=True,
+                       keep_state=True).run(models, np.zeros(len(models)))
+    check_served(res, models, "random models, concurrent")
