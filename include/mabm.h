@@ -139,6 +139,24 @@ typedef struct mabm_sim mabm_sim;
 mabm_status mabm_create_sim(const mabm_config* cfg, void* device_arena, size_t arena_bytes,
                             void* hip_stream, mabm_sim** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): create a
+ * simulation like mabm_create_sim, but in the library's static arena on
+ * the current device instead of a caller's arena.  The arena is a
+ * file-scope device array of 64 MiB (2^26 bytes) per device, held by every
+ * device the library runs on until the process ends; a configuration whose
+ * mabm_arena_bytes exceeds it is rejected with E_NOMEM.  The call allocates
+ * no device memory (no hipMalloc or allocating library routine), and the
+ * simulation's steps run as direct kernel launches, never as graphs (the
+ * MABM_FLAG_NO_GRAPH flag is forced), so stepping it allocates none either.
+ * One device's arena holds one simulation at a time: a second call on the
+ * device before mabm_destroy_sim of the first returns E_STATE.  The arena
+ * keeps the last simulation's contents; everything a simulation needs
+ * cleared is cleared when its model is finalized.  Host threads that use
+ * the arena of one device must not overlap (they would race on it).
+ * Other arguments, ownership and errors as mabm_create_sim. */
+mabm_status mabm_create_sim_static(const mabm_config* cfg, void* hip_stream, mabm_sim** out);
+
 /* Add a species (Sec. 2: molecular species with diffusion from
  * Stokes-Einstein, initial concentration -> count, localisation ->
  * compartment).  Ids 0, 1, ... in call order.  E_STATE after the model is

@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         L.mabm_arena_bytes.restype = c.c_size_t
         L.mabm_arena_bytes.argtypes = [c.POINTER(Config), c.c_uint32, c.c_uint32]
         L.mabm_create_sim.argtypes = [c.POINTER(Config), P, c.c_size_t, P, c.POINTER(P)]
+        L.mabm_create_sim_static.argtypes = [c.POINTER(Config), P, c.POINTER(P)]
         L.mabm_add_species.argtypes = [P, c.c_char_p, c.c_float, c.c_uint32, c.c_int32,
                                        c.POINTER(c.c_int32)]
         L.mabm_add_rule.argtypes = [P, c.POINTER(Rule), c.POINTER(c.c_int32)]
@@ -101,7 +102,7 @@ def lib() -> ctypes.CDLL:
         L.mabm_get_param.argtypes = [P, c.c_int32, P]
         L.mabm_last_error.restype = c.c_char_p
         L.mabm_last_error.argtypes = [P]
-        for name in ("mabm_create_sim", "mabm_add_species", "mabm_add_rule", "mabm_grid",
+        for name in ("mabm_create_sim", "mabm_create_sim_static", "mabm_add_species", "mabm_add_rule", "mabm_grid",
                      "mabm_step", "mabm_counts", "mabm_size", "mabm_export", "mabm_import",
                      "mabm_profile", "mabm_profile_read", "mabm_agent_updates", "mabm_digest",
                      "mabm_destroy_sim", "mabm_create_batch", "mabm_set_initial_counts",
@@ -136,11 +137,14 @@ class Sim:
     """One simulation on the GPU.  ``model`` is a workloads.Model (species,
     rules, geometry, dt, seed, capacity).  By default the simulation gets its
     own HIP stream; ``graphs=True`` replays each step as a captured HIP graph
-    (measured slightly slower than direct launches on ROCm 7.2)."""
+    (measured slightly slower than direct launches on ROCm 7.2).
+    ``static_arena=True`` creates it in the library's static device arena
+    (mabm_create_sim_static, for callers that cannot allocate): no arena
+    tensor is allocated, and steps are direct launches."""
 
     def __init__(self, model, record: bool = False, cell_um: Optional[float] = None,
                  capacity: Optional[int] = None, stream=None, device: str = "cuda",
-                 arena=None, graphs: bool = False):
+                 arena=None, graphs: bool = False, static_arena: bool = False):
         import torch
         L = lib()
         self.n_species = len(model.species)
@@ -149,16 +153,26 @@ class Sim:
                                         len(model.rules)))
         if nbytes == 0:
             raise MabmError(E_INVALID, "invalid configuration")
-        self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8,
-                                                                  device=device)
+        if static_arena:
+            self.arena = None
+            dev = torch.device(device)
+        else:
+            self.arena = arena if arena is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                                      device=device)
+            dev = self.arena.device
         if stream is None:
-            stream = torch.cuda.Stream(self.arena.device)
-            stream.wait_stream(torch.cuda.current_stream(self.arena.device))
+            stream = torch.cuda.Stream(dev)
+            stream.wait_stream(torch.cuda.current_stream(dev))
         self.stream = stream
+        self.device = dev
         h = ctypes.c_void_p()
-        rc = L.mabm_create_sim(ctypes.byref(self.cfg), ctypes.c_void_p(self.arena.data_ptr()),
-                               self.arena.numel(), ctypes.c_void_p(self.stream.cuda_stream),
-                               ctypes.byref(h))
+        if static_arena:
+            rc = L.mabm_create_sim_static(ctypes.byref(self.cfg),
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        else:
+            rc = L.mabm_create_sim(ctypes.byref(self.cfg), ctypes.c_void_p(self.arena.data_ptr()),
+                                   self.arena.numel(), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h))
         if rc != OK:
             raise MabmError(rc, L.mabm_last_error(None).decode())
         self._h = h
@@ -271,7 +285,7 @@ class Sim:
             self._ring = None
             return
         words = int(L.mabm_ring_entry_bytes(self._h)) // 8
-        dev = self.arena.device
+        dev = self.device
         ring = torch.zeros(entries * words, dtype=torch.int64, device=dev)
         # the zero fill runs on the current stream: the simulation's stream,
         # which writes the entries, waits for it, and the caching allocator
@@ -351,6 +365,7 @@ class Batch(Sim):
             stream = torch.cuda.Stream(self.arena.device)
             stream.wait_stream(torch.cuda.current_stream(self.arena.device))
         self.stream = stream
+        self.device = self.arena.device
         h = ctypes.c_void_p()
         rc = L.mabm_create_batch(ctypes.cast(self.cfgs, ctypes.c_void_p), self.n_sims,
                                  ctypes.c_void_p(self.arena.data_ptr()), self.arena.numel(),

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -179,6 +180,7 @@ struct mabm_sim {
     std::vector<SpeciesHost> species;
     std::vector<mabm_rule> rules;
     bool finalized = false, failed = false, has_bimol = false;
+    int static_device = -1;  // device whose static arena holds this simulation (-1: none)
     // captured steps (one step, and graph_steps steps) per starting state:
     // parity, agent buffer and steps since the last binning
     std::map<uint32_t, hipGraphExec_t> graphs;
@@ -714,6 +716,20 @@ mabm_status create_impl(const mabm_config* cs, uint32_t n, void* device_arena, s
     return MABM_OK;
 }
 
+// The static arena of mabm_create_sim_static: device memory that needs no
+// allocation call, for callers that cannot allocate.  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// the array's name is no device address: the address on a device is taken
+// once, with that device current, by hipGetSymbolAddress, and only that
+// address is ever handed to kernels or copies.
+constexpr size_t kStaticArenaBytes = size_t(64) << 20;
+constexpr int kMaxStaticDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kStaticArenaBytes];
+
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
+bool g_static_busy[kMaxStaticDevices] = {};
+
 }  // namespace
 
 extern "C" {
@@ -742,6 +758,57 @@ mabm_status mabm_create_batch(const mabm_config* cfgs, uint32_t n_sims, void* de
                               size_t arena_bytes, void* hip_stream, mabm_sim** out)
 {
     return create_impl(cfgs, n_sims, device_arena, arena_bytes, hip_stream, out);
+}
+
+mabm_status mabm_create_sim_static(const mabm_config* cfg, void* hip_stream, mabm_sim** out)
+{
+    if (!out) return MABM_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    if (!batch_ok(cfg, 1, why)) {
+        g_create_error = why;
+        return MABM_E_INVALID;
+    }
+    const size_t need = make_layout(cfg, 1).total;
+    if (need > kStaticArenaBytes) {
+        g_create_error = "the configuration needs " + std::to_string(need) +
+                         " device bytes; the static arena holds " +
+                         std::to_string(kStaticArenaBytes) + " (use mabm_create_sim with an arena)";
+        return MABM_E_NOMEM;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return MABM_E_DEVICE;
+    }
+    if (dev < 0 || dev >= kMaxStaticDevices) {
+        g_create_error = "device index beyond the static arenas";
+        return MABM_E_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev]) {
+        g_create_error = "the static arena of this device holds a simulation already";
+        return MABM_E_STATE;
+    }
+    if (!g_static_ptr[dev]) {
+        // once per device, with the device current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_create_error = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+            return MABM_E_DEVICE;
+        }
+        g_static_ptr[dev] = p;
+    }
+    // no graph is ever instantiated for it: steps are direct launches
+    mabm_config c = *cfg;
+    c.flags |= MABM_FLAG_NO_GRAPH;
+    const mabm_status st = create_impl(&c, 1, g_static_ptr[dev], kStaticArenaBytes, hip_stream, out);
+    if (st != MABM_OK) return st;
+    (*out)->static_device = dev;
+    g_static_busy[dev] = true;
+    return MABM_OK;
 }
 
 mabm_status mabm_add_species(mabm_sim* s, const char* name, float D, uint32_t count, int32_t comp,
@@ -1364,6 +1431,10 @@ mabm_status mabm_destroy_sim(mabm_sim* s)
     for (EventPair& p : s->pool) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
+    }
+    if (s->static_device >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[s->static_device] = false;
     }
     delete s;
     return MABM_OK;
