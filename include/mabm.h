@@ -83,10 +83,23 @@ typedef struct {
     float inner_radius_um; /* NESTED_SPHERES nucleus radius, um */
     float dt_s;            /* time step, s (> 0) */
     uint64_t seed;         /* Philox key */
-    uint32_t capacity;     /* maximum live agents at any step end */
+    uint32_t capacity;     /* maximum live agents at any step end (see below) */
     float cell_um;         /* spatial-hash cell size, um; 0 = chosen by the library */
     uint32_t flags;        /* MABM_FLAG_* */
 } mabm_config;
+
+/* Capacity.  A step whose end leaves more live agents than the capacity
+ * (births and removals of that step counted as the step definition's
+ * compaction counts them) makes the simulation fail with E_CAPACITY,
+ * reported by the next synchronising call, exactly at the step where the
+ * definition overflows, whatever the binning interval.  Agents removed in a
+ * step keep their array slots until a binning compacts them, or until a
+ * child of a later step that keeps the binning takes the slot over, so the
+ * agent arrays hold the capacity plus a quarter more (mabm_arena_bytes
+ * includes it); only a step whose pair rules remove more than that quarter
+ * while the live agents are near the capacity runs out of slots, which is
+ * E_CAPACITY too, with its own message.  A step's children are not
+ * otherwise limited (up to one per live agent). */
 
 /* Record, for every live agent, the cell id, unimolecular event and partner
  * of the last step, so that mabm_export can return them.  Costs extra
@@ -234,8 +247,9 @@ mabm_status mabm_import(mabm_sim* sim, uint32_t n, const uint32_t* id, const uin
  * initial_count applies to all of them until mabm_set_initial_counts sets
  * one count per simulation; mabm_counts returns the per-species totals over
  * the batch; mabm_grid gives simulation 0's grid; mabm_size, mabm_export and
- * mabm_import are E_STATE (use the mabm_batch_* calls).  The 4,096 births per
- * step are shared by the whole batch.
+ * mabm_import are E_STATE (use the mabm_batch_* calls).  Each simulation's
+ * capacity holds for it alone (E_CAPACITY names the first simulation that
+ * overflowed); the slots are pooled.
  * ---------------------------------------------------------------------- */
 
 /* Device bytes of a batch (0 if the configurations are invalid or

@@ -76,17 +76,33 @@ bool config_ok(const mabm_config* c, std::string& why)
     // (slot indices then stay below the extra-chain markers)
     static_assert((1u << 30) < kUnlinked, "slot indices below the chain markers");
     if (c->capacity == 0 || c->capacity > (1u << 30)) { why = "capacity must be in [1, 2^30]"; return false; }
+    static_assert((1u << 30) + (1u << 28) + 1024 < kUnlinked, "slots of 2^30 agents below the chain markers");
     if (c->cell_um < 0.0f) { why = "cell_um must be >= 0"; return false; }
     return true;
 }
 
+// Per-simulation counters, kSimWords arrays of n_sims words in the arena, in
+// this order: live, dead[0], dead[1], born[0], born[1], next_id[0],
+// next_id[1] (SimCounters).
+constexpr int kSimWords = 7;
+
 // Arena layout: every array 256-byte aligned, in this order.
 struct Layout {
     size_t ctl, tab, rec[2], id[2], rank, event, sclaim, cell_count, cell_start, tile_acc, slot,
-        prop, plist, rkey, revent, rpartner, births, counts, digest, next_id, head, nxt, glob,
-        total;
+        prop, plist, rkey, revent, rpartner, births, bkey, brank, hlist, counts, digest, simc,
+        head, nxt, glob, total;
     uint32_t ncells, ntiles, tile_shift;
+    uint32_t capacity, slots;
 };
+
+// Entries of the agent arrays for a summed capacity: the capacity plus a
+// quarter for holes.  Agents that a step removes occupy their slots until a
+// binning drops them, or until a child of a later step that keeps the
+// binning takes the slot over; a step's children go after the slots in
+// use.  The slots in use therefore stay within the live agents plus the
+// removals of a single step's pair rules, and the headroom covers removals
+// of up to a quarter of the capacity in one step.
+uint64_t slots_for(uint64_t capacity) { return capacity + capacity / 4 + 1024; }
 
 // Layout of one simulation (n = 1) or of a batch of n: agent arrays sized
 // for the summed capacities, the simulations' cell grids one after another
@@ -106,6 +122,10 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
         cap += cs[k].capacity;
         cells += (size_t)1 << (3 * morton_bits(grid_from_config(cs[k])));
     }
+    const size_t births = cap;  // a parent has at most one child per step
+    L.capacity = (uint32_t)cap;
+    L.slots = (uint32_t)slots_for(cap);
+    cap = L.slots;  // every per-slot array
     L.ncells = (uint32_t)cells;
     L.tile_shift = 0;
     while (((cells + ((size_t)kScanTile << L.tile_shift) - 1) >> (kScanTileLog + L.tile_shift)) >
@@ -120,7 +140,7 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     }
     L.rank = take(cap * 4);
     L.event = take(cap);
-    L.sclaim = take((cap + kClaimChunk - 1) / kClaimChunk * kClaimChunk);
+    L.sclaim = take((cap + kClaimChunk - 1) / kClaimChunk * kClaimChunk);  // whole chunks
     const size_t padded = (size_t)L.ntiles << (kScanTileLog + L.tile_shift);  // whole scan tiles
     L.cell_count = take(padded * 4);
     L.cell_start = take((padded + 1) * 4);
@@ -131,10 +151,13 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.rkey = take(cap * 4);
     L.revent = take(cap);
     L.rpartner = take(cap * 4);
-    L.births = take((size_t)kMaxBirthsPerStep * sizeof(Birth));
+    L.births = take(births * sizeof(Birth));
+    L.bkey = take(births * 8);
+    L.brank = take(births * 8);
+    L.hlist = take(cap * 4);
     L.counts = take((size_t)kMaxSpecies * 8 * n);
     L.digest = take((size_t)8 * n);
-    L.next_id = take((size_t)4 * n);
+    L.simc = take((size_t)4 * kSimWords * n);
     L.head = take((padded + 1) * 4);
     L.nxt = take(cap * 4);
     L.glob = take(cap * 4);
@@ -166,7 +189,7 @@ struct mabm_sim {
     std::vector<Tables> tabs;          // one per simulation
     std::vector<uint32_t> sim_G;
     std::vector<float> sim_h;
-    std::vector<uint32_t> host_next_id;  // staging for the per-simulation id counters
+    std::vector<uint32_t> host_simc;     // staging for the per-simulation counters
     uint64_t steps_done = 0;             // steps enqueued since finalize
     // counts ring (caller's device memory): entries of ring_words u64
     unsigned long long* ring = nullptr;
@@ -294,6 +317,15 @@ bool may_keep_binning(const mabm_sim* s)
     return false;
 }
 
+// whether the model has rules with children (splits, emissions)
+bool has_births(const mabm_sim* s)
+{
+    for (const mabm_rule& u : s->rules)
+        if (u.kind == MABM_UNIMOL && (u.placement == MABM_SPLIT || u.placement == MABM_EMIT))
+            return true;
+    return false;
+}
+
 // whether the model has rules that place agents (births, translocations)
 bool places_agents(const mabm_sim* s)
 {
@@ -321,6 +353,7 @@ mabm_status build_one(mabm_sim* s, uint32_t k_sim, Tables& T)
     T.Rin2 = (float)((double)c.inner_radius_um * (double)c.inner_radius_um);
     T.key0 = (uint32_t)c.seed;
     T.key1 = (uint32_t)(c.seed >> 32);
+    T.capacity = c.capacity;
     uint64_t acc = 0;
     for (int k = 0; k < ns; ++k) {
         acc += s->sim_counts[k][k_sim];
@@ -559,13 +592,27 @@ void fill_dev(mabm_sim* s)
     d.revent = A + L.revent;
     d.rpartner = (uint32_t*)(A + L.rpartner);
     d.births = (Birth*)(A + L.births);
+    d.bkey = (unsigned long long*)(A + L.bkey);
+    d.brank = (uint2*)(A + L.brank);
+    d.hlist = (uint32_t*)(A + L.hlist);
     d.counts = (unsigned long long*)(A + L.counts);
     d.digest = (unsigned long long*)(A + L.digest);
-    d.next_id = (uint32_t*)(A + L.next_id);
+    {
+        uint32_t* c = (uint32_t*)(A + L.simc);
+        const size_t n = s->n_sims;
+        d.sc.live = c;
+        d.sc.dead[0] = c + n;
+        d.sc.dead[1] = c + 2 * n;
+        d.sc.born[0] = c + 3 * n;
+        d.sc.born[1] = c + 4 * n;
+        d.sc.next_id[0] = c + 5 * n;
+        d.sc.next_id[1] = c + 6 * n;
+    }
     d.head = (uint32_t*)(A + L.head);
     d.nxt = (uint32_t*)(A + L.nxt);
     d.glob = (uint32_t*)(A + L.glob);
-    d.capacity = (uint32_t)total_capacity(s->cfgs.data(), s->n_sims);
+    d.capacity = L.capacity;
+    d.slots = L.slots;
     d.n_sims = s->n_sims;
 }
 
@@ -602,15 +649,24 @@ mabm_status finalize(mabm_sim* s, bool place)
     Ctl c{};
     c.s[0] = StepState{0u, d.n_init, d.n_init, 0u};
     HIP_OK(s, hipMemcpyAsync(d.ctl, &c, sizeof c, hipMemcpyHostToDevice, s->stream));
-    s->host_next_id = n_init;
-    HIP_OK(s, hipMemcpyAsync(d.next_id, s->host_next_id.data(), 4 * s->n_sims,
+    // per simulation: live agents and next ids from the placement, no
+    // removals or children yet
+    const size_t n = s->n_sims;
+    s->host_simc.assign(kSimWords * n, 0u);
+    for (size_t k = 0; k < n; ++k) {
+        s->host_simc[k] = n_init[k];          // live
+        s->host_simc[5 * n + k] = n_init[k];  // next_id[0]
+    }
+    HIP_OK(s, hipMemcpyAsync(d.sc.live, s->host_simc.data(), 4 * s->host_simc.size(),
                              hipMemcpyHostToDevice, s->stream));
+    d.birth_blocks = has_births(s) ? kBirthSortBlocks : 0u;
+    d.span = has_births(s) ? d.slots : d.capacity;
     // cell counts and both parities' tile sums start at zero
     HIP_OK(s, hipMemsetAsync(d.cell_count, 0, ((size_t)d.ntiles << (kScanTileLog + d.tile_shift)) * 4,
                              s->stream));
     HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
     // claim slots are all-ones between steps (each step resets those it used)
-    HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.capacity * 8, s->stream));
+    HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.slots * 8, s->stream));
     launch_fill_records(d, s->stream);
     if (place)
         for (uint32_t k = 0; k < s->n_sims; ++k) {
@@ -628,15 +684,39 @@ mabm_status finalize(mabm_sim* s, bool place)
     return MABM_OK;
 }
 
+// Synchronises the stream and reads the control block and the
+// per-simulation counters; reports the sticky device errors, and checks the
+// last step's end against each simulation's capacity (the device checks
+// every earlier step's end at the start of the next one).
 mabm_status sync_ctl(mabm_sim* s, Ctl* out)
 {
+    const size_t n = s->n_sims;
+    s->host_simc.resize(kSimWords * n);
     HIP_OK(s, hipMemcpyAsync(out, s->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(s, hipMemcpyAsync(s->host_simc.data(), s->dev.sc.live, 4 * s->host_simc.size(),
+                             hipMemcpyDeviceToHost, s->stream));
     HIP_OK(s, hipStreamSynchronize(s->stream));
     if (out->err) {
         s->failed = true;
         if (out->err & kErrPlacement) return fail(s, MABM_E_DEVICE, "initial placement failed after 64 attempts");
-        if (out->err & kErrBirths) return fail(s, MABM_E_CAPACITY, "more than 4096 births in one step");
-        return fail(s, MABM_E_CAPACITY, "agent capacity exceeded by births");
+        if (out->err & kErrCapacity)
+            return fail(s, MABM_E_CAPACITY, "live agents exceeded the capacity at the end of a step");
+        return fail(s, MABM_E_CAPACITY,
+                    "agent slots exhausted: one step's pair rules removed more agents than the "
+                    "slot headroom (a quarter of the capacity) while the live agents were near it");
+    }
+    // the last step (parity s->parity ^ 1): live at its start, less its
+    // removals, plus its children
+    const int q = s->parity ^ 1;
+    const uint32_t* c = s->host_simc.data();
+    for (size_t k = 0; k < n; ++k) {
+        const uint64_t live = (uint64_t)c[k] - c[(1 + q) * n + k] + c[(3 + q) * n + k];
+        if (live > s->cfgs[k].capacity) {
+            s->failed = true;
+            return fail(s, MABM_E_CAPACITY,
+                        "live agents exceeded the capacity at the end of a step (simulation " +
+                            std::to_string(k) + ")");
+        }
     }
     return MABM_OK;
 }
@@ -1098,64 +1178,43 @@ mabm_status export_impl(mabm_sim* s, uint32_t sim, uint32_t capacity, uint32_t* 
     Ctl ctl{};
     st = sync_ctl(s, &ctl);
     if (st != MABM_OK) return st;
-    const uint32_t n_slots = ctl.s[s->parity].n_slots;
-    const Agents& A = s->dev.a[s->buf];
-    // slot ranges that can hold the simulation's agents: all slots for a
-    // single simulation; in a batch, its initial block before any step, and
-    // after one its cells' run of the cell-sorted array plus the last step's
-    // births, appended after the binned agents
-    std::vector<std::pair<uint32_t, uint32_t>> ranges;
-    if (s->n_sims == 1) {
-        ranges.push_back({0u, n_slots});
-    } else if (s->steps_done == 0) {
-        const Tables& T = s->tabs[sim];
-        ranges.push_back({T.slot_base, T.slot_base + T.init_end[T.ns - 1]});
-    } else {
-        const Tables& T = s->tabs[sim];
-        uint32_t cs[2];
-        HIP_OK(s, hipMemcpyAsync(&cs[0], s->dev.cell_start + T.cell_base, 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(&cs[1], s->dev.cell_start + T.cell_base + (1u << (3 * T.morton_bits)), 4,
-                                 hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipStreamSynchronize(s->stream));
-        ranges.push_back({cs[0], cs[1]});
-        if (n_slots > ctl.n_binned) ranges.push_back({ctl.n_binned, n_slots});
-    }
-    size_t n = 0;
-    for (auto& r : ranges) n += r.second - r.first;
-    std::vector<uint4> hr(n);
-    std::vector<uint32_t> hid(n), hk(n), hp(n);
-    std::vector<uint8_t> hs(n), he(n);
-    size_t off = 0;
-    for (auto& r : ranges) {
-        const size_t m = r.second - r.first, b = r.first;
-        if (!m) continue;
-        HIP_OK(s, hipMemcpyAsync(hr.data() + off, A.rec + b, m * 16, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hid.data() + off, A.id + b, m * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hk.data() + off, s->dev.rkey + b, m * 4, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(he.data() + off, s->dev.revent + b, m, hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(s, hipMemcpyAsync(hp.data() + off, s->dev.rpartner + b, m * 4, hipMemcpyDeviceToHost, s->stream));
-        off += m;
-    }
-    HIP_OK(s, hipStreamSynchronize(s->stream));
-    std::vector<uint32_t> idx;
-    idx.reserve(n);
-    for (uint32_t i = 0; i < (uint32_t)n; ++i) {
-        hs[i] = (uint8_t)(hr[i].w & 0xFFu);
-        if (hs[i] != kDead && (hr[i].w >> kMetaSimShift) == sim) idx.push_back(i);
-    }
-    if (idx.size() > capacity) return fail(s, MABM_E_INVALID, "export buffer smaller than the live agents");
-    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return hid[a] < hid[b]; });
+    // the device gathers the simulation's live agents (wherever births and
+    // holes have put them) into arrays that are free between steps
     const bool rec = (s->cfg.flags & MABM_FLAG_RECORD) != 0;
-    for (size_t k = 0; k < idx.size(); ++k) {
-        const uint32_t i = idx[k];
-        if (id) id[k] = hid[i];
-        if (species) species[k] = hs[i];
-        if (x) std::memcpy(&x[k], &hr[i].x, 4);
-        if (y) std::memcpy(&y[k], &hr[i].y, 4);
-        if (z) std::memcpy(&z[k], &hr[i].z, 4);
-        if (key) key[k] = rec ? hk[i] : MABM_NONE;
-        if (event) event[k] = (rec && he[i] != kNoEvent) ? (int32_t)he[i] : -1;
-        if (partner) partner[k] = rec ? hp[i] : MABM_NONE;
+    Dev d = state_dev(s);
+    HIP_OK(s, hipMemsetAsync(&d.ctl->export_n, 0, 4, s->stream));
+    launch_export(d, s->parity, sim, rec ? 1 : 0, s->stream);
+    HIP_OK(s, hipGetLastError());
+    uint32_t n = 0;
+    HIP_OK(s, hipMemcpyAsync(&n, &d.ctl->export_n, 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_OK(s, hipStreamSynchronize(s->stream));
+    if (n > d.capacity) return fail(s, MABM_E_CAPACITY, "more live agents than the capacity");
+    if (n > capacity) return fail(s, MABM_E_INVALID, "export buffer smaller than the live agents");
+    std::vector<Birth> hb(n);
+    std::vector<unsigned long long> hk(rec ? n : 0);
+    std::vector<uint8_t> he(rec ? n : 0);
+    if (n) {
+        HIP_OK(s, hipMemcpyAsync(hb.data(), d.births, (size_t)n * sizeof(Birth), hipMemcpyDeviceToHost,
+                                 s->stream));
+        if (rec) {
+            HIP_OK(s, hipMemcpyAsync(hk.data(), d.bkey, (size_t)n * 8, hipMemcpyDeviceToHost, s->stream));
+            HIP_OK(s, hipMemcpyAsync(he.data(), d.event, n, hipMemcpyDeviceToHost, s->stream));
+        }
+        HIP_OK(s, hipStreamSynchronize(s->stream));
+    }
+    std::vector<uint32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return hb[a].parent < hb[b].parent; });
+    for (size_t k = 0; k < n; ++k) {
+        const Birth& g = hb[idx[k]];
+        if (id) id[k] = g.parent;
+        if (species) species[k] = (uint8_t)(g.sp & 0xFFu);
+        if (x) x[k] = g.x;
+        if (y) y[k] = g.y;
+        if (z) z[k] = g.z;
+        if (key) key[k] = rec ? (uint32_t)(hk[idx[k]] >> 32) : MABM_NONE;
+        if (event) event[k] = (rec && he[idx[k]] != kNoEvent) ? (int32_t)he[idx[k]] : -1;
+        if (partner) partner[k] = rec ? (uint32_t)hk[idx[k]] : MABM_NONE;
     }
     return MABM_OK;
 }
@@ -1217,6 +1276,12 @@ mabm_status mabm_import(mabm_sim* s, uint32_t n, const uint32_t* id, const uint8
     Ctl ctl{};
     ctl.s[0] = StepState{t, n, next_id, 0u};
     HIP_OK(s, hipMemcpyAsync(s->dev.ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, s->stream));
+    // one simulation: n live agents, ids from next_id
+    s->host_simc.assign(kSimWords, 0u);
+    s->host_simc[0] = n;
+    s->host_simc[5] = next_id;
+    HIP_OK(s, hipMemcpyAsync(s->dev.sc.live, s->host_simc.data(), 4 * kSimWords, hipMemcpyHostToDevice,
+                             s->stream));
     HIP_OK(s, hipStreamSynchronize(s->stream));
     s->parity = 0;
     s->buf = 0;
@@ -1290,11 +1355,8 @@ mabm_status mabm_batch_size(mabm_sim* s, uint32_t sim, uint32_t* n_live, uint32_
         *n_live = (uint32_t)std::accumulate(c.begin() + (size_t)sim * kMaxSpecies,
                                             c.begin() + (size_t)(sim + 1) * kMaxSpecies, 0ull);
     if (next_id) {
-        if (s->n_sims == 1) {
-            *next_id = ctl.s[s->parity].next_id;
-        } else {
-            HIP_OK(s, hipMemcpy(next_id, s->dev.next_id + sim, 4, hipMemcpyDeviceToHost));
-        }
+        // sync_ctl (through live_counts) read the per-simulation counters
+        *next_id = s->host_simc[(5 + s->parity) * s->n_sims + sim];
     }
     return MABM_OK;
 }

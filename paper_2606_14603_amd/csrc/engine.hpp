@@ -22,6 +22,7 @@ static_assert(kMaxRules <= 255, "rule indices fit a byte beside kNoRule");
 // array.
 constexpr uint32_t kMetaBusy = 1u << 8;     // had a unimolecular event this step
 constexpr uint32_t kMetaClaimer = 1u << 9;  // non-busy agent of a claiming species
+constexpr uint32_t kMetaListed = 1u << 10;  // a hole already in the hole list
 constexpr uint32_t kMetaSimShift = 16;
 constexpr uint32_t kMetaSimMask = 0xFFFF0000u;
 constexpr uint32_t kMaxSims = 65535;
@@ -35,7 +36,13 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kEnd = 0x7FFFFFFFu;
 constexpr uint32_t kUnlinked = 0x7FFFFFFEu;
 constexpr uint32_t kGlobBit = 0x80000000u;
-constexpr uint32_t kMaxBirthsPerStep = 4096;  // births ranked by one workgroup
+// Births of a step are ranked by (simulation, parent id): runs of kBirthRun
+// records are sorted in LDS by kBirthSortBlocks workgroups, and each birth's
+// rank is its rank in its own run plus its lower bound in every other run.
+constexpr uint32_t kBirthRun = 256;
+constexpr uint32_t kBirthRunLog = 8;
+static_assert(kBirthRun == 1u << kBirthRunLog, "birth runs are a power of two");
+constexpr uint32_t kBirthSortBlocks = 32;
 constexpr uint32_t kTileStride = 1024;        // words between tile counters (4 KiB)
 constexpr int kScanItems = 8;                 // cells per thread in the scan
 constexpr int kScanThreads = 256;
@@ -57,8 +64,10 @@ enum Purpose : uint32_t { kInit = 0, kMove = 2, kPair = 3, kPrio = 4, kBirth = 5
 enum Geometry : int32_t { kBox = 0, kSphere = 1, kNested = 2 };
 enum Placement : int32_t { kKeep = 0, kSplit = 1, kEmit = 2, kTranslocate = 3 };
 
-// sticky device error bits
-enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrBirths = 4u };
+// sticky device error bits: a simulation's live agents above its capacity
+// at a step's end; an initial placement that failed; more slots needed than
+// the arrays hold (the capacity plus the headroom for holes, see Dev::slots)
+enum ErrBit : uint32_t { kErrCapacity = 1u, kErrPlacement = 2u, kErrSlots = 4u };
 
 struct RuleDev {
     int32_t kind, placement, p0, p1, to;
@@ -91,7 +100,8 @@ struct Tables {
     uint32_t morton_bits;  // cells are sorted by the Morton (Z-order) index of their
                            // coordinates over a 2^bits grid per axis
     uint32_t key0, key1;   // Philox key (seed low, high)
-    uint32_t pad0, pad1;
+    uint32_t capacity;     // the simulation's most live agents at a step's end
+    uint32_t pad1;
     // position of this simulation in a batch (all zero for a single one):
     // its index, its first cell in the batch's cell order, its first slot
     // at placement
@@ -120,22 +130,32 @@ struct Tables {
 struct StepState {
     uint32_t t;        // step counter
     uint32_t n_slots;  // entries of the agent arrays (holes included)
-    uint32_t next_id;
-    uint32_t pad;
+    uint32_t next_id;  // (a single simulation; a batch keeps one per simulation)
+    uint32_t h_used;   // entries of the hole list already refilled by births
 };
 
 struct Ctl {
     StepState s[2];
     uint32_t n_births[2];  // birth records appended by the step of parity p
-    uint32_t holes[2];     // agents consumed by pair rules in the step of parity p
     uint32_t n_prop[2];    // entries of the proposer list of the step of parity p
     uint32_t n_binned;     // agents binned by the last binning (births follow them)
-    uint32_t uni_dead[2];  // agents removed by unimolecular rules in the step of parity p
-    uint32_t dead_base;    // holes at the step's start older than the previous step's
-                           // pair rules (steps that keep the binning compact nothing)
+    uint32_t h_n;          // entries of the hole list since the last binning
     uint32_t n_glob;       // entries of the global list of agents placed again
+    uint32_t export_n;     // agents gathered by the last export
     uint32_t err;          // ErrBit, sticky
+    uint32_t pad;
     unsigned long long agent_updates;  // sum of live agents at step starts
+};
+
+// Per-simulation counters, n_sims entries each, the step-indexed ones
+// double-buffered by parity like the step scalars: live agents at the
+// current step's start; agents removed and born by the step of parity p;
+// the next id to assign at the start of the step of parity p.
+struct SimCounters {
+    uint32_t* live;
+    uint32_t* dead[2];
+    uint32_t* born[2];
+    uint32_t* next_id[2];
 };
 
 struct Birth {
@@ -166,16 +186,30 @@ struct Dev {
     uint32_t* rkey;        // record arrays, indexed like the current agents
     uint8_t* revent;
     uint32_t* rpartner;
-    Birth* births;
+    Birth* births;               // this step's birth records (births_cap)
+    unsigned long long* bkey;    // birth runs sorted by (simulation << 32 | parent id)
+    uint2* brank;                // per birth record: its rank in its run, and the
+                                 // records of smaller simulations in the run
+    uint32_t* hlist;             // slots of holes since the binning (kept steps refill them)
     unsigned long long* counts;  // [n_sims][kMaxSpecies]
     unsigned long long* digest;  // [n_sims], state digests (queries only)
-    uint32_t* next_id;           // batch: per simulation, the next id to assign
+    SimCounters sc;
     uint32_t* head;              // per cell: first agent of its extra chain (kEnd: none)
     uint32_t* nxt;               // per slot: next agent of its chain, kUnlinked, kGlobBit
     uint32_t* glob;              // agents placed twice since the binning
     uint32_t link;               // keep extra chains (kept binnings with placements)
-    uint32_t capacity, ncells, ntiles, n_init;
+    // capacity: live agents of all simulations together (the sum of their
+    // capacities), which also bounds the births of a step; slots: entries of
+    // the agent arrays, the capacity plus headroom for holes (agents removed
+    // in a step occupy their slots until a binning drops them, or a birth of
+    // a later step that keeps the binning takes the slot over)
+    uint32_t capacity, slots, ncells, ntiles, n_init;
+    // slots the agent-indexed kernels cover: all of them for a model with
+    // children, else the capacity (without children the slots in use never
+    // exceed it)
+    uint32_t span;
     uint32_t tile_shift;         // a scan tile is kScanTile << tile_shift cells
+    uint32_t birth_blocks;       // workgroups sorting birth runs (0: the model has no births)
     uint32_t n_sims;             // 1: a single simulation; tab has n_sims entries
     // launch shape of the neighbour search (performance only; results do
     // not depend on them): lanes per claimer (0: 4 for the 8-cell stencil,
@@ -218,5 +252,10 @@ void launch_fill_records(const Dev& d, hipStream_t s);
 // per-simulation digests of the live agents (id, species, position bits)
 // into out[n_sims] (verification queries)
 void launch_digest(const Dev& d, int cur, unsigned long long* out, hipStream_t s);
+// gathers simulation `sim`'s live agents into the birth records (id in
+// parent, meta in sp), and with `record` their last-step cell ids and
+// partners into bkey and events into `event`, counting them in
+// ctl->export_n (queries between steps, when these arrays are free)
+void launch_export(const Dev& d, int cur, uint32_t sim, int record, hipStream_t s);
 
 }  // namespace mabm

@@ -65,9 +65,9 @@ __device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) -
 // contiguous run of chunks, so chunks that gather from the same neighbouring
 // cells share one L2.  It is a bijection of [0, gridDim.x).
 constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_chunk()
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t n)
 {
-    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t b = blockIdx.x;
     const uint32_t q = n / kXcds, r = n % kXcds, x = b % kXcds;
     return x * q + (x < r ? x : r) + b / kXcds;
 }
@@ -92,6 +92,20 @@ __device__ __forceinline__ uint32_t run_add(uint32_t key, uint32_t* counter, uin
         base = atomicAdd(&counter[size_t(key) * stride], uint32_t(next_head - lane));
     base = __shfl(base, head_lane, 64);
     return base + uint32_t(lane - head_lane);
+}
+
+// Appends the lanes with `flag` to a list with one atomic on its length per
+// wave; returns each flagged lane's index in the list (others: 0).  Called
+// by all lanes of the wave.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* length, bool flag)
+{
+    const uint64_t m = __ballot(flag);
+    if (!m) return 0u;
+    const int leader = __builtin_ctzll(m);
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(length, uint32_t(__popcll(m)));
+    base = __shfl(base, leader, 64);
+    return base + uint32_t(__popcll(m & lanes_below()));
 }
 
 // Runs f(u) once for every distinct simulation index u among the active
@@ -170,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Dev d)
 __global__ void __launch_bounds__(kBlock) k_fill_records(Dev d)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.capacity) return;
+    if (i >= d.slots) return;
     d.rkey[i] = kNone;
     d.revent[i] = kNoEvent;
     d.rpartner[i] = kNone;
@@ -222,11 +236,39 @@ __device__ void release_offset(const Tables& T, const RuleDev& R, uint32_t id, u
     ux = uy = uz = 0.0f;
 }
 
-__device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent, uint32_t sp_sim,
-                                           float x, float y, float z)
+// Adds, for every simulation u among the active lanes, their number to
+// counter[u] (one atomic per simulation present).  The lanes are grouped by
+// comparing their own simulation indices: the active lanes of a branch may
+// belong to several simulations even inside per_sim, whose waterfall the
+// compiler may dissolve into per-lane table loads.
+__device__ __forceinline__ void add_by_sim(uint32_t* counter, uint32_t sim)
 {
-    const uint32_t k = atomicAdd(&d.ctl->n_births[p], 1u);
-    if (k < kMaxBirthsPerStep) d.births[k] = Birth{parent, sp_sim, x, y, z};
+    uint64_t left = __ballot(1);
+    while (left) {
+        const uint32_t u = __shfl(sim, __builtin_ctzll(left), 64);
+        const uint64_t mine = __ballot(sim == u);
+        if (lane_id() == __builtin_ctzll(mine)) atomicAdd(&counter[u], uint32_t(__popcll(mine)));
+        left &= ~mine;
+    }
+}
+
+// A child of this step (a split's second product or an emission) from the
+// lanes that take this branch: its record is appended to the step's birth
+// records with one atomic per wave, and its simulation's children counted.
+__device__ __forceinline__ void append_child(const Dev& d, int p, uint32_t sim, const Birth& b)
+{
+    const uint32_t k = wave_append(&d.ctl->n_births[p], true);
+    add_by_sim(d.sc.born[p], sim);
+    if (k < d.capacity) d.births[k] = b;
+}
+
+// A slot that became a hole in a step that keeps the binning, from the
+// lanes that take this branch: listed (one atomic per wave) for the
+// children of this and later steps to refill.
+__device__ __forceinline__ void list_hole(const Dev& d, uint32_t i)
+{
+    const uint32_t k = wave_append(&d.ctl->h_n, true);
+    d.hlist[k % d.slots] = i;
 }
 
 // ---------------------------------------------------------------------------
@@ -239,7 +281,8 @@ __device__ __forceinline__ void push_birth(const Dev& d, int p, uint32_t parent,
 // agent stays in slot i, so its claimer flag (2 if its species searches the
 // 27-cell stencil this step, as the search decides) and recorded fields are
 // written here instead of by scatter.  Returns whether a unimolecular rule
-// removed the agent.
+// removed the agent; a child of a split or an emission is appended to the
+// step's birth records.
 template <bool B>
 __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const Agents& A, int p,
                                            int record, int bin, uint32_t moved, uint32_t i,
@@ -330,7 +373,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
                 cy = wrap_box(T, cy);
                 cz = wrap_box(T, cz);
             }
-            push_birth(d, p, id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz);
+            append_child(d, p, T.sim, Birth{id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz});
             break;
         }
         default: {  // kEmit
@@ -342,16 +385,21 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
                 cy = wrap_box(T, cy);
                 cz = wrap_box(T, cz);
             }
-            push_birth(d, p, id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz);
+            append_child(d, p, T.sim, Birth{id, uint32_t(R.p1) | (B ? r.w & kMetaSimMask : 0u), cx, cy, cz});
             break;
         }
         }
     }
     const uint32_t sim_bits = B ? r.w & kMetaSimMask : 0u;
     if (dies) {
-        // a hole until the next binning drops it
-        A.rec[i].w = uint32_t(kDead) | sim_bits;
-        if (!bin) d.sclaim[i] = 0;
+        // a hole until the next binning drops it, or (in a step that keeps
+        // the binning) a later birth takes the slot over
+        A.rec[i].w = uint32_t(kDead) | sim_bits | (bin ? 0u : kMetaListed);
+        if (!bin) {
+            d.sclaim[i] = 0;
+            list_hole(d, i);
+        }
+        add_by_sim(d.sc.dead[p], T.sim);
         return true;
     }
     const uint32_t meta = fs | (ev >= 0 ? kMetaBusy : 0u) | sim_bits;
@@ -414,21 +462,22 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int b
         id = A.id[i];
     }
     const uint32_t s = r.w & 0xFFu;
-    bool died = false;
     if (s != kDead) {
         if (B)
             per_sim(sim_of(r.w), [&](uint32_t u) {
-                died = move_agent<true>(d, d.tab[u], A, p, record, bin, moved, i, id, t, r, s, key);
+                move_agent<true>(d, d.tab[u], A, p, record, bin, moved, i, id, t, r, s, key);
             });
         else
-            died = move_agent<false>(d, *d.tab, A, p, record, bin, moved, i, id, t, r, s, key);
+            move_agent<false>(d, *d.tab, A, p, record, bin, moved, i, id, t, r, s, key);
     } else if (!bin && i < n) {
         d.sclaim[i] = 0;  // a hole kept in its slot
+        // an agent removed by an earlier step's pair rule joins the hole list
+        // once (its record is marked listed)
+        if (!(r.w & kMetaListed)) {
+            A.rec[i].w = r.w | kMetaListed;
+            list_hole(d, i);
+        }
     }
-    // removals, for the count of live agents (one atomic per wave that has any)
-    const uint64_t gone = __ballot(died);
-    if (gone && lane_id() == __ffsll((long long)gone) - 1)
-        atomicAdd(&d.ctl->uni_dead[p], uint32_t(__popcll(gone)));
     if (!bin) return;
     // rank within the cell, and the per-tile sums the scan starts from
     const uint32_t rank = run_add(key, d.cell_count, 1u);
@@ -436,6 +485,253 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int b
     if (i < n) d.rank[i] = key == kNone ? kNone : rank;
 }
 
+// ---------------------------------------------------------------------------
+// births (O9).  The children of a step take ids in parent-id order, per
+// simulation: child of rank r among its simulation's children gets id
+// next_id + r.  The rank is found without a global sort: the step's birth
+// records (appended by move in any order) are cut into runs of kBirthRun;
+// each run is sorted in LDS by its key (simulation << 32 | parent id; keys
+// are unique, a parent having at most one child per step), which gives
+// every record its rank in its own run and the number of records of
+// smaller simulations there; a record's rank among all births is then its
+// rank in its run plus, for every other run, the number of keys below its
+// own (a binary search).  Slots follow the same order: a binning step
+// appends the children after the binned agents; a step that keeps the
+// binning first refills the holes listed since the binning, then appends.
+// ---------------------------------------------------------------------------
+static_assert(kBirthRun == kBlock, "one birth record per thread of a sorting workgroup");
+
+__device__ __forceinline__ unsigned long long birth_key(const Birth& b)
+{
+    return ((unsigned long long)(b.sp >> kMetaSimShift) << 32) | b.parent;
+}
+
+// Workgroup w of n_w sorts runs w, w + n_w, ...: bitonic sort of the run's
+// (key, index) pairs in LDS, padded with all-ones keys; the sorted keys go
+// to bkey, and each record's rank in the run and the number of the run's
+// records of smaller simulations to brank.
+__device__ void sort_birth_runs(const Dev& d, int p, uint32_t w, uint32_t n_w)
+{
+    __shared__ unsigned long long key[kBirthRun];
+    __shared__ uint32_t pos[kBirthRun];
+    const uint32_t nb = min(d.ctl->n_births[p], d.capacity);
+    const uint32_t j = threadIdx.x;
+    for (uint32_t run = w; run * kBirthRun < nb; run += n_w) {
+        const uint32_t lo = run * kBirthRun;
+        const uint32_t m = min(kBirthRun, nb - lo);
+        key[j] = j < m ? birth_key(d.births[lo + j]) : ~0ull;
+        pos[j] = j;
+        __syncthreads();
+        for (uint32_t k = 2; k <= kBirthRun; k <<= 1) {
+            for (uint32_t h = k >> 1; h > 0; h >>= 1) {
+                const uint32_t l = j ^ h;
+                if (l > j) {
+                    const bool up = (j & k) == 0;
+                    const unsigned long long a = key[j], c = key[l];
+                    if ((a > c) == up) {
+                        key[j] = c;
+                        key[l] = a;
+                        const uint32_t t = pos[j];
+                        pos[j] = pos[l];
+                        pos[l] = t;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (j < m) {
+            const unsigned long long kj = key[j];
+            d.bkey[lo + j] = kj;
+            // first position of this record's simulation in the sorted run
+            const unsigned long long first = kj & 0xFFFFFFFF00000000ull;
+            uint32_t x = 0, y = j;
+            while (x < y) {
+                const uint32_t mid = (x + y) >> 1;
+                if (key[mid] < first) x = mid + 1;
+                else y = mid;
+            }
+            d.brank[lo + pos[j]] = uint2{j, x};
+        }
+        __syncthreads();  // the run's LDS is reused by the next one
+    }
+}
+
+// keys of a sorted run below `key`
+__device__ __forceinline__ uint32_t count_below(const unsigned long long* run, uint32_t len,
+                                                unsigned long long key)
+{
+    uint32_t x = 0, y = len;
+    while (x < y) {
+        const uint32_t mid = (x + y) >> 1;
+        if (run[mid] < key) x = mid + 1;
+        else y = mid;
+    }
+    return x;
+}
+
+// Slots of a step's children: a binning step appends them after the binned
+// agents (base = the binned count); a step that keeps the binning first
+// refills the listed holes not yet refilled (m of them), then appends after
+// its slots (base = the slot count).
+struct BirthSlots {
+    uint32_t base, m, h_used;
+};
+
+__device__ __forceinline__ BirthSlots birth_slots(const Dev& d, const StepState& cur, bool bin,
+                                                  uint32_t nb)
+{
+    if (bin) return BirthSlots{d.ctl->n_binned, 0u, 0u};
+    const uint32_t avail = d.ctl->h_n - cur.h_used;
+    return BirthSlots{cur.n_slots, nb < avail ? nb : avail, cur.h_used};
+}
+
+// Places birth record k of the step (nb records; their runs sorted): its
+// rank by (simulation, parent id) gives its slot and its id.  The child
+// takes no part in its birth step's search (busy flag); while a binning is
+// kept it heads the extra chain of its cell, or, in a refilled hole that
+// already lies in a chain, joins the global list.
+template <bool B>
+__device__ void place_birth(const Dev& d, int p, const Agents& A, uint32_t k, uint32_t nb, bool bin,
+                            const BirthSlots& bs, int record)
+{
+    const Birth bb = d.births[k];
+    const unsigned long long key = birth_key(bb);
+    const uint2 br = d.brank[k];
+    uint32_t r = br.x, smaller = br.y;
+    const uint32_t runs = (nb + kBirthRun - 1) >> kBirthRunLog;
+    if (runs > 1) {
+        const uint32_t own = k >> kBirthRunLog;
+        for (uint32_t q = 0; q < runs; ++q) {
+            if (q == own) continue;
+            const unsigned long long* run = d.bkey + (size_t(q) << kBirthRunLog);
+            const uint32_t len = min(kBirthRun, nb - (q << kBirthRunLog));
+            r += count_below(run, len, key);
+            if (B) smaller += count_below(run, len, key & 0xFFFFFFFF00000000ull);
+        }
+    }
+    const uint32_t sim = B ? bb.sp >> kMetaSimShift : 0u;
+    const uint32_t j = r < bs.m ? d.hlist[(bs.h_used + r) % d.slots] : bs.base + (r - bs.m);
+    if (j >= d.slots) return;  // the bookkeeping reports the overflow
+    A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp | kMetaBusy);
+    A.id[j] = d.sc.next_id[p][sim] + (r - (B ? smaller : 0u));
+    if (record) {
+        d.rkey[j] = kNone;
+        d.revent[j] = kNoEvent;
+        d.rpartner[j] = kNone;
+    }
+    if (d.link) {
+        const Tables& T = d.tab[sim];
+        uint32_t cell = cell_of(T, bb.x, bb.y, bb.z);
+        if (B) cell += T.cell_base;
+        if (r >= bs.m) {
+            d.nxt[j] = atomicExch(&d.head[cell], j);  // a fresh slot
+        } else {
+            const uint32_t old = d.nxt[j];
+            if ((old & ~kGlobBit) == kUnlinked) {
+                d.nxt[j] = atomicExch(&d.head[cell], j);
+            } else if (!(old & kGlobBit)) {
+                d.nxt[j] = old | kGlobBit;
+                d.glob[atomicAdd(&d.ctl->n_glob, 1u)] = j;
+            }
+        }
+    }
+}
+
+// The step's bookkeeping (O9, O10), run by one whole workgroup while the
+// other workgroups of its kernel place the step's children:
+//   - per simulation, the live agents at this step's start (those at the
+//     previous step's start, less its removals, plus its children) are
+//     checked against the simulation's capacity (a step whose end exceeds
+//     it raises the sticky capacity error here, or at the next query if it
+//     is the last step run) and summed into the agent-update count; the
+//     next step's first id is this one's plus this step's children;
+//   - the next step's slot count: a binning step's binned agents plus its
+//     children; a kept step's slots plus the children that did not refill
+//     a hole (the arrays hold `slots` entries: more is the slot error).
+template <bool B>
+__device__ void bookkeeping(const Dev& d, int p, bool bin)
+{
+    __shared__ unsigned long long live_part[kBlock / 64];
+    __shared__ uint32_t over_part[kBlock / 64];
+    Ctl* ctl = d.ctl;
+    const StepState cur = ctl->s[p];
+    const SimCounters& sc = d.sc;
+    unsigned long long live_sum = 0;
+    uint32_t over = 0;
+    for (uint32_t k = threadIdx.x; k < d.n_sims; k += kBlock) {
+        const uint32_t live = sc.live[k] - sc.dead[p ^ 1][k] + sc.born[p ^ 1][k];
+        sc.live[k] = live;
+        sc.dead[p ^ 1][k] = 0u;
+        sc.born[p ^ 1][k] = 0u;
+        sc.next_id[p ^ 1][k] = sc.next_id[p][k] + sc.born[p][k];
+        over |= live > d.tab[k].capacity ? 1u : 0u;
+        live_sum += live;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        live_sum += __shfl_xor(live_sum, o, 64);
+        over |= __shfl_xor(over, o, 64);
+    }
+    if (lane_id() == 0) {
+        live_part[threadIdx.x >> 6] = live_sum;
+        over_part[threadIdx.x >> 6] = over;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        uint32_t bad = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            tot += live_part[w];
+            bad |= over_part[w];
+        }
+        const uint32_t nb_all = ctl->n_births[p];
+        const uint32_t nb = min(nb_all, d.capacity);
+        const BirthSlots bs = birth_slots(d, cur, bin, nb);
+        uint64_t slots_next = uint64_t(bs.base) + (nb - bs.m);
+        uint32_t err = bad ? kErrCapacity : 0u;
+        if (nb_all > d.capacity || slots_next > d.slots) {
+            err |= kErrSlots;
+            if (slots_next > d.slots) slots_next = d.slots;
+        }
+        if (err) atomicOr(&ctl->err, err);
+        ctl->agent_updates += tot;
+        ctl->n_births[p ^ 1] = 0u;
+        ctl->n_prop[p ^ 1] = 0u;
+        if (bin) {
+            // a new binning: no holes yet (the binned agents are compacted),
+            // no extra chains, no agents placed twice
+            ctl->h_n = 0u;
+            ctl->n_glob = 0u;
+        }
+        ctl->s[p ^ 1] = StepState{cur.t + 1u, uint32_t(slots_next), cur.next_id + nb,
+                                  bin ? 0u : bs.h_used + bs.m};
+    }
+}
+
+// Births and bookkeeping of a binning step, run by the extra workgroups of
+// the scatter launch: the last one does the bookkeeping, all of them place
+// the step's children after the binned agents in the sorted buffer.
+template <bool B>
+__device__ void scatter_births(const Dev& d, int p, int record, uint32_t w, uint32_t n_w)
+{
+    const uint32_t nb = min(d.ctl->n_births[p], d.capacity);
+    const BirthSlots bs = birth_slots(d, d.ctl->s[p], true, nb);
+    for (uint32_t k = w * kBlock + threadIdx.x; k < nb; k += n_w * kBlock)
+        place_birth<B>(d, p, d.a[p ^ 1], k, nb, true, bs, record);
+    if (w == n_w - 1) {
+        // the scan has read this parity's tile sums (and cleared the
+        // other's): clear them too, so that steps keeping this binning need
+        // not
+        uint32_t* acc = tile_acc(d, p);
+        for (uint32_t k = threadIdx.x; k < d.ntiles; k += kBlock) acc[size_t(k) * kTileStride] = 0u;
+        bookkeeping<B>(d, p, true);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scatter: binned agents to cell order in the other buffer; the claimer flag
+// (non-busy agent of a claiming species) is set in the record and in the
+// one-byte array the propose chunks scan.
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // scan of the cell counts, one launch, no waiting between workgroups: each
 // tile sums the earlier tiles' totals (accumulated by move), scans its 2048
@@ -483,6 +779,11 @@ __device__ __forceinline__ uint32_t block_excl_scan_sum(uint32_t v, uint32_t r, 
 
 __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
 {
+    if (blockIdx.x >= d.ntiles) {
+        // the workgroups after the tiles sort the step's birth runs
+        sort_birth_runs(d, p, blockIdx.x - d.ntiles, gridDim.x - d.ntiles);
+        return;
+    }
     const uint32_t tile = blockIdx.x;
     const uint32_t npass = 1u << d.tile_shift;
     constexpr int kVec = kScanItems / 4;
@@ -547,171 +848,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan(Dev d, int p)
     }
 }
 
-// ---------------------------------------------------------------------------
-// births (O9): child r of the step, ranked by parent id among the step's
-// births (ranks by counting: parent ids are distinct, as a parent has at most
-// one child per step), goes to slot base + r of A with id next_id + r (in a
-// batch, slots follow (simulation, parent id) and ids are per simulation).
-// A child takes no part in its birth step's search (busy flag).  While a
-// binning is kept, each child also heads the extra chain of its cell.  Run
-// by one whole workgroup; returns the births placed and sets *err (then
-// none is placed).
-// ---------------------------------------------------------------------------
-constexpr uint32_t kRankLds = 1024;  // births ranked from LDS; more read from L2
-
 template <bool B>
-__device__ uint32_t place_births(const Dev& d, int p, const Agents& A, uint32_t base,
-                                 uint32_t next_id, int record, uint32_t* err)
+__device__ __forceinline__ void scatter_slot(const Dev& d, int p, int record, uint32_t i)
 {
-    __shared__ uint32_t skey[kRankLds], ssim[kRankLds];
-    uint32_t nb = d.ctl->n_births[p];
-    *err = 0;
-    if (nb > kMaxBirthsPerStep) {
-        *err = kErrBirths;
-        nb = 0;
-    } else if (uint64_t(base) + nb > d.capacity) {
-        *err = kErrCapacity;
-        nb = 0;
-    }
-    const bool in_lds = nb <= kRankLds;
-    if (in_lds)
-        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
-            const Birth bb = d.births[k];
-            skey[k] = bb.parent;
-            ssim[k] = bb.sp >> kMetaSimShift;
-        }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
-        const Birth bb = d.births[k];
-        const uint32_t sim = bb.sp >> kMetaSimShift;
-        uint32_t r = 0, rs = 0;  // rank among all births, among the simulation's births
-        for (uint32_t m = 0; m < nb; ++m) {
-            uint32_t pm, sm;
-            if (in_lds) {
-                pm = skey[m];
-                sm = ssim[m];
-            } else {
-                const Birth o = d.births[m];
-                pm = o.parent;
-                sm = o.sp >> kMetaSimShift;
-            }
-            if (B) {
-                r += (sm < sim || (sm == sim && pm < bb.parent)) ? 1u : 0u;
-                rs += (sm == sim && pm < bb.parent) ? 1u : 0u;
-            } else {
-                r += pm < bb.parent ? 1u : 0u;
-            }
-        }
-        const uint32_t j = base + r;
-        A.rec[j] = make_rec(bb.x, bb.y, bb.z, bb.sp | kMetaBusy);
-        A.id[j] = B ? d.next_id[sim] + rs : next_id + r;
-        if (record) {
-            d.rkey[j] = kNone;
-            d.revent[j] = kNoEvent;
-            d.rpartner[j] = kNone;
-        }
-        if (d.link) {
-            const Tables& T = d.tab[B ? sim : 0u];
-            uint32_t key = cell_of(T, bb.x, bb.y, bb.z);
-            if (B) key += T.cell_base;
-            d.nxt[j] = atomicExch(&d.head[key], j);
-        }
-    }
-    if (B) {
-        // every id is assigned; each simulation's counter advances by its
-        // number of births, added by its last-ranked birth
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nb; k += kBlock) {
-            const Birth bb = d.births[k];
-            const uint32_t sim = bb.sp >> kMetaSimShift;
-            uint32_t rs = 0, ns = 0;
-            for (uint32_t m = 0; m < nb; ++m) {
-                const uint32_t sm = in_lds ? ssim[m] : d.births[m].sp >> kMetaSimShift;
-                const uint32_t pm = in_lds ? skey[m] : d.births[m].parent;
-                ns += sm == sim ? 1u : 0u;
-                rs += (sm == sim && pm < bb.parent) ? 1u : 0u;
-            }
-            if (rs + 1u == ns) d.next_id[sim] += ns;
-        }
-    }
-    return nb;
-}
-
-// Births and bookkeeping of a binning step (O9, O10), run by the extra last
-// workgroup of the scatter launch: births follow the binned agents in the
-// sorted buffer; then the next step's scalars.
-template <bool B>
-__device__ void births_and_bookkeeping(const Dev& d, int p, int record)
-{
-    Ctl* ctl = d.ctl;
-    const StepState cur = ctl->s[p];
-    const uint32_t nbin = ctl->n_binned;
-    uint32_t err;
-    const uint32_t nb = place_births<B>(d, p, d.a[p ^ 1], nbin, cur.next_id, record, &err);
-    // the scan has read this parity's tile sums (and cleared the other's):
-    // clear them too, so that steps keeping this binning need not
-    uint32_t* acc = tile_acc(d, p);
-    for (uint32_t k = threadIdx.x; k < d.ntiles; k += kBlock) acc[size_t(k) * kTileStride] = 0u;
-    if (threadIdx.x == 0) {
-        if (err) atomicOr(&ctl->err, err);
-        // live agents at this step's start: its slots minus the holes in
-        // them (the previous step's pair rules', and any older ones kept by
-        // steps that did not bin); the binning has dropped them all
-        ctl->agent_updates += cur.n_slots - ctl->dead_base - ctl->holes[p ^ 1];
-        ctl->dead_base = 0u;
-        ctl->uni_dead[p] = 0u;
-        ctl->holes[p ^ 1] = 0u;
-        ctl->n_births[p ^ 1] = 0u;
-        ctl->n_prop[p ^ 1] = 0u;
-        ctl->n_glob = 0u;
-        ctl->s[p ^ 1] = StepState{cur.t + 1u, nbin + nb, cur.next_id + nb, 0u};
-    }
-}
-
-// Births and bookkeeping of a step that keeps the previous step's cell
-// lists (there is no scan or scatter; run by the first workgroup of finish,
-// after the search): births follow the step's slots in place, nothing is
-// compacted, and holes are carried to the next step (both parities' tile
-// sums are already clear: the binning's scatter cleared the ones its scan
-// had read).
-template <bool B>
-__device__ void kept_bookkeeping(const Dev& d, int p, int record)
-{
-    Ctl* ctl = d.ctl;
-    const StepState cur = ctl->s[p];
-    uint32_t err;
-    const uint32_t nb = place_births<B>(d, p, d.a[p ^ 1], cur.n_slots, cur.next_id, record, &err);
-    if (threadIdx.x == 0) {
-        if (err) atomicOr(&ctl->err, err);
-        const uint32_t prev_holes = ctl->holes[p ^ 1];
-        ctl->agent_updates += cur.n_slots - ctl->dead_base - prev_holes;
-        ctl->dead_base += prev_holes + ctl->uni_dead[p];
-        ctl->uni_dead[p] = 0u;
-        ctl->holes[p ^ 1] = 0u;
-        ctl->n_births[p ^ 1] = 0u;
-        ctl->n_prop[p ^ 1] = 0u;
-        ctl->s[p ^ 1] = StepState{cur.t + 1u, cur.n_slots + nb, cur.next_id + nb, 0u};
-    }
-}
-
-// ---------------------------------------------------------------------------
-// scatter: binned agents to cell order in the other buffer; the claimer flag
-// (non-busy agent of a claiming species) is set in the record and in the
-// one-byte array the propose chunks scan.
-// ---------------------------------------------------------------------------
-template <bool B>
-__global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
-{
-    if (blockIdx.x == gridDim.x - 1) {
-        births_and_bookkeeping<B>(d, p, record);
-        return;
-    }
-    const Tables& T = *d.tab;
-    const uint32_t n = d.ctl->s[p].n_slots;
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
     const uint32_t rank = d.rank[i];
     if (rank == kNone) return;
+    const Tables& T = *d.tab;
     const Agents A = d.a[p];
     const Agents O = d.a[p ^ 1];
     uint4 r = A.rec[i];
@@ -741,6 +883,19 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record)
         d.revent[j] = d.event[i];
         d.rpartner[j] = kNone;
     }
+}
+
+// The first agent_blocks workgroups cover the slots (one agent per
+// thread); the rest place the step's children and do its bookkeeping.
+template <bool B>
+__global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record, uint32_t agent_blocks)
+{
+    if (blockIdx.x >= agent_blocks) {
+        scatter_births<B>(d, p, record, blockIdx.x - agent_blocks, gridDim.x - agent_blocks);
+        return;
+    }
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < d.ctl->s[p].n_slots) scatter_slot<B>(d, p, record, i);
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
@@ -839,6 +994,7 @@ struct PairLds {
     float dmax[kMaxSpecies];   // and how far one step moves its targets at most
 };
 
+template <bool B>
 __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, const Agents& A,
                                          const uint4& rk, uint32_t k, uint32_t self, uint32_t s,
                                          float x, float y, float z, int comp, float r2max,
@@ -859,6 +1015,10 @@ __device__ __forceinline__ void consider(const Tables& T, const PairLds& P, cons
     const uint32_t rv = sb < uint32_t(kMaxSpecies) ? P.rule_of[s * kMaxSpecies + sb] : kNoRule;
     const int r = rv == kNoRule ? -1 : int(rv);
     if (k == self || r < 0 || (rk.w & kMetaBusy)) return;
+    // in a batch a slot of this simulation's cell lists may hold another
+    // simulation's child (a refilled hole), and the global list holds every
+    // simulation's agents
+    if (B && sim_of(rk.w) != T.sim) return;
     if (T.geometry == kNested && compartment(T, bx, by, bz) != comp) return;
     if (!(d2 <= P.r2[r])) return;
     if (b.idx != kNone && d2 > b.d2) return;
@@ -975,10 +1135,10 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         if (a1) r1 = A.rec[k0 + 1];
         if (b0) r2 = A.rec[k1];
         if (b1) r3 = A.rec[k1 + 1];
-        if (a0) consider(T, P, A, r0, k0, j, s, x, y, z, comp, r2max, b);
-        if (a1) consider(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, r2max, b);
-        if (b0) consider(T, P, A, r2, k1, j, s, x, y, z, comp, r2max, b);
-        if (b1) consider(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, r2max, b);
+        if (a0) consider<B>(T, P, A, r0, k0, j, s, x, y, z, comp, r2max, b);
+        if (a1) consider<B>(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, r2max, b);
+        if (b0) consider<B>(T, P, A, r2, k1, j, s, x, y, z, comp, r2max, b);
+        if (b1) consider<B>(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, r2max, b);
         k0 += 2;
         k1 += 2;
     }
@@ -986,15 +1146,12 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         // agents placed since the binning: the cells' extra chains, and the
         // global list (agents placed twice), shared among the group's lanes
         for (uint32_t k = h0; k != kEnd; k = d.nxt[k] & ~kGlobBit)
-            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+            consider<B>(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
         for (uint32_t k = h1; k != kEnd; k = d.nxt[k] & ~kGlobBit)
-            consider(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
+            consider<B>(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
         for (uint32_t q = uint32_t(li); q < n_glob; q += uint32_t(width)) {
             const uint32_t k = d.glob[q];
-            const uint4 rk = A.rec[k];
-            // a batch's global list holds the agents of every simulation
-            if (B && sim_of(rk.w) != T.sim) continue;
-            consider(T, P, A, rk, k, j, s, x, y, z, comp, r2max, b);
+            consider<B>(T, P, A, A.rec[k], k, j, s, x, y, z, comp, r2max, b);
         }
     }
     reduce_best(b, width, top);
@@ -1027,22 +1184,28 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 
 template <bool B>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
-k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
+k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search_blocks)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint4 plocal[kPropLds];
     __shared__ PairLds P;
     __shared__ uint32_t count, nprop, pbase;
+    if (blockIdx.x >= search_blocks) {
+        // a step that keeps the binning sorts its birth runs here (after
+        // move has appended them, before finish places them)
+        sort_birth_runs(d, p, blockIdx.x - search_blocks, gridDim.x - search_blocks);
+        return;
+    }
     const Tables& T = *d.tab;
     // `split` workgroups share a chunk (small simulations, whose few chunks
     // would otherwise leave the claimers to a few workgroups): each compacts
     // the chunk and searches every split-th pass of its claimers
-    const uint32_t g = xcd_chunk();
+    const uint32_t g = xcd_chunk(search_blocks);
     const uint32_t share = g % split;
     const uint32_t first = g / split * kPChunk;
     // The thread's four claimer flags, requested first.  The flag array is
-    // padded to whole chunks and the grid covers the capacity, so the word
-    // is in bounds even past the live agents (whose count arrives with the
+    // padded to whole chunks and the grid covers the slots, so the word is
+    // in bounds even past the live agents (whose count arrives with the
     // control block).
     const uint32_t word =
         *reinterpret_cast<const FlagWord*>(d.sclaim + first + uint32_t(kClaimPer) * threadIdx.x);
@@ -1125,23 +1288,31 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved)
 // confirmed pair writes, and of a mutual homotypic pair only the lower id).
 // The proposer entry carries the rule and whether the target claims too, so
 // a confirmation reads only the two slots and the target's id and proposal.
-// Species are written as single bytes, leaving the flag bytes alone.
+// Species are written as single bytes, leaving the flag bytes alone.  In a
+// step that keeps the binning, finish also places the step's children (its
+// whole grid) and does the bookkeeping (its first workgroup).
 // ---------------------------------------------------------------------------
 template <bool B>
 __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int bin)
 {
-    __shared__ uint32_t s_holes;
+    __shared__ uint32_t s_dead;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
-    if (!bin && blockIdx.x == 0) kept_bookkeeping<B>(d, p, record);
     // the thread's first proposer entry is requested with the list's length
     // (entries past it are stale but inside the list's capacity)
     uint32_t q = blockIdx.x * kBlock + threadIdx.x;
-    uint4 e = q < d.capacity ? d.plist[q] : uint4{};
+    uint4 e = q < d.slots ? d.plist[q] : uint4{};
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
+    if (!bin) {
+        const uint32_t nb = min(ctl->n_births[p], d.capacity);
+        const BirthSlots bs = birth_slots(d, ctl->s[p], false, nb);
+        for (uint32_t k = q; k < nb; k += gridDim.x * kBlock)
+            place_birth<B>(d, p, d.a[p ^ 1], k, nb, false, bs, record);
+        if (blockIdx.x == 0) bookkeeping<B>(d, p, false);
+    }
     if (blockIdx.x * kBlock >= np) return;
-    if (threadIdx.x == 0) s_holes = 0;
+    if (threadIdx.x == 0) s_dead = 0;
     __syncthreads();
     const Agents A = d.a[p ^ 1];
     for (; q < np; q += gridDim.x * kBlock) {
@@ -1164,14 +1335,19 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
         set_species(A, j, R.p0 < 0 ? kDead : uint32_t(R.p0));
         set_species(A, b, R.p1 < 0 ? kDead : uint32_t(R.p1));
         const uint32_t h = (R.p0 < 0 ? 1u : 0u) + (R.p1 < 0 ? 1u : 0u);
-        if (h) atomicAdd(&s_holes, h);
+        if (h) {
+            // removals of the pair's simulation (a single simulation's are
+            // summed per workgroup first)
+            if (B) atomicAdd(&d.sc.dead[p][e.w >> 16], h);
+            else atomicAdd(&s_dead, h);
+        }
         if (record) {
             d.rpartner[j] = idb;
             d.rpartner[b] = ida;
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && s_holes) atomicAdd(&ctl->holes[p], s_holes);
+    if (!B && threadIdx.x == 0 && s_dead) atomicAdd(&d.sc.dead[p][0], s_dead);
 }
 
 // per-species counts of live agents (LDS histogram, one atomic per species
@@ -1286,6 +1462,30 @@ __global__ void __launch_bounds__(kBlock) k_digest(Dev d, int cur, unsigned long
     if (acc_sim != kNone && lane_id() == 0) atomicAdd(&out[acc_sim], acc);
 }
 
+// Gathers simulation `sim`'s live agents (queries between steps): the
+// record and id of each go to the birth records, its recorded cell id and
+// partner to bkey and its recorded event to `event`, at an index from one
+// atomic per wave; ctl->export_n counts them (cleared by the caller).
+__global__ void __launch_bounds__(kBlock) k_export(Dev d, int cur, uint32_t sim, int record)
+{
+    const uint32_t n = d.ctl->s[cur].n_slots;
+    const Agents A = d.a[cur];
+    const uint32_t stride = gridDim.x * kBlock;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; (i & ~63u) < n; i += stride) {
+        uint4 r = {0u, 0u, 0u, kDead};
+        if (i < n) r = A.rec[i];
+        const bool mine = (r.w & 0xFFu) != kDead && sim_of(r.w) == sim;
+        const uint32_t k = wave_append(&d.ctl->export_n, mine);
+        if (!mine || k >= d.capacity) continue;
+        d.births[k] = Birth{A.id[i], r.w, __uint_as_float(r.x), __uint_as_float(r.y),
+                            __uint_as_float(r.z)};
+        if (record) {
+            d.bkey[k] = ((unsigned long long)d.rkey[i] << 32) | d.rpartner[i];
+            d.event[k] = d.revent[i];
+        }
+    }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, uint32_t n)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -1318,7 +1518,7 @@ void launch_init(const Dev& d, hipStream_t s)
 }
 void launch_fill_records(const Dev& d, hipStream_t s)
 {
-    k_fill_records<<<blocks_for(d.capacity), kBlock, 0, s>>>(d);
+    k_fill_records<<<blocks_for(d.slots), kBlock, 0, s>>>(d);
     const uint32_t cells = (d.ntiles << (kScanTileLog + d.tile_shift)) + 1u;
     k_fill_heads<<<blocks_for(cells), kBlock, 0, s>>>(d, cells);
 }
@@ -1335,33 +1535,41 @@ void launch_move(const Dev& d, int p, int record, int bin, uint32_t moved, hipSt
                  const KEvents& ev)
 {
     if (d.n_sims > 1)
-        go(k_move<true>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin, moved);
-    else go(k_move<false>, blocks_for(d.capacity), kBlock, s, ev, d, p, record, bin, moved);
+        go(k_move<true>, blocks_for(d.span), kBlock, s, ev, d, p, record, bin, moved);
+    else go(k_move<false>, blocks_for(d.span), kBlock, s, ev, d, p, record, bin, moved);
 }
 
 void launch_scan(const Dev& d, int p, hipStream_t s, const KEvents& ev)
 {
-    go(k_scan, d.ntiles, kScanThreads, s, ev, d, p);
+    // the tiles, then the birth-run sorters (models that place children)
+    go(k_scan, d.ntiles + d.birth_blocks, kScanThreads, s, ev, d, p);
 }
 void launch_scatter(const Dev& d, int p, int record, hipStream_t s, const KEvents& ev)
 {
-    // one workgroup per 256 slots, plus the births/bookkeeping workgroup
-    if (d.n_sims > 1) go(k_scatter<true>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
-    else go(k_scatter<false>, blocks_for(d.capacity) + 1, kBlock, s, ev, d, p, record);
+    // one workgroup per 256 slots, then the workgroups that place the
+    // children (at least one: it also does the bookkeeping)
+    const unsigned agents = blocks_for(d.span);
+    const unsigned grid = agents + (d.birth_blocks ? d.birth_blocks : 1u);
+    if (d.n_sims > 1) go(k_scatter<true>, grid, kBlock, s, ev, d, p, record, agents);
+    else go(k_scatter<false>, grid, kBlock, s, ev, d, p, record, agents);
 }
 void launch_propose(const Dev& d, int p, int bin, uint32_t moved, hipStream_t s, const KEvents& ev)
 {
     // enough workgroups to fill the chip: chunks shared by up to 16
-    const unsigned chunks = chunks_for(d.capacity);
+    const unsigned chunks = chunks_for(d.span);
     unsigned split = 1;
     const unsigned min_blocks = d.prop_min_blocks ? d.prop_min_blocks : kPropMinBlocks;
     while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
-    if (d.n_sims > 1) go(k_propose<true>, chunks * split, kBlock, s, ev, d, p, split, bin, moved);
-    else go(k_propose<false>, chunks * split, kBlock, s, ev, d, p, split, bin, moved);
+    // a step that keeps the binning sorts its birth runs in extra workgroups
+    const unsigned search = chunks * split;
+    const unsigned grid = search + (bin ? 0u : d.birth_blocks);
+    if (d.n_sims > 1) go(k_propose<true>, grid, kBlock, s, ev, d, p, split, bin, moved, search);
+    else go(k_propose<false>, grid, kBlock, s, ev, d, p, split, bin, moved, search);
 }
 void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {
-    // a fixed grid strides over the step's proposer list
+    // a fixed grid strides over the step's proposer list (and a kept step's
+    // children)
     unsigned nb = blocks_for(d.capacity);
     if (nb > kFinishBlocks) nb = kFinishBlocks;
     if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record, bin);
@@ -1372,10 +1580,17 @@ void launch_digest(const Dev& d, int cur, unsigned long long* out, hipStream_t s
     k_zero_u64<<<blocks_for(d.n_sims), kBlock, 0, s>>>(out, d.n_sims);
     // about 4,096 waves, each over a whole number of 64-slot rounds
     const uint32_t waves = 4096;
-    uint32_t per_wave = (d.capacity + waves - 1) / waves;
+    uint32_t per_wave = (d.slots + waves - 1) / waves;
     per_wave = (per_wave + 63u) / 64u * 64u;
-    const uint32_t need = (d.capacity + per_wave - 1) / per_wave;  // waves that have slots
+    const uint32_t need = (d.slots + per_wave - 1) / per_wave;  // waves that have slots
     k_digest<<<(need + 3) / 4, kBlock, 0, s>>>(d, cur, out, per_wave);
+}
+
+void launch_export(const Dev& d, int cur, uint32_t sim, int record, hipStream_t s)
+{
+    unsigned nb = blocks_for(d.slots);
+    if (nb > 4096) nb = 4096;
+    k_export<<<nb, kBlock, 0, s>>>(d, cur, sim, record);
 }
 
 void launch_counts(const Dev& d0, int cur, hipStream_t s, unsigned long long* dst,
@@ -1385,10 +1600,10 @@ void launch_counts(const Dev& d0, int cur, hipStream_t s, unsigned long long* ds
     if (dst) d.counts = dst;
     k_zero_counts<<<blocks_for(d.n_sims * uint32_t(kMaxSpecies)), kBlock, 0, s>>>(d, cur, tslot);
     if (d.n_sims > 1) {
-        k_counts_batch<<<blocks_for(d.capacity), kBlock, 0, s>>>(d, cur);
+        k_counts_batch<<<blocks_for(d.slots), kBlock, 0, s>>>(d, cur);
         return;
     }
-    unsigned nb = blocks_for(d.capacity);
+    unsigned nb = blocks_for(d.slots);
     if (nb > 2048) nb = 2048;
     k_counts<<<nb, kBlock, 0, s>>>(d, cur);
 }

@@ -65,15 +65,22 @@ def test_capacity_overflow_is_sticky(mabm):
         s.step(1)
 
 
-def test_births_per_step_limit_reported(mabm):
+def test_five_thousand_births_in_one_step_are_placed(mabm):
+    # every gene emits in the first step: 5,000 children ranked by parent id
+    # over twenty sorted runs, ids next_id.. in parent order
+    import oracle
+    from parity import assert_same
     m = W.Model("burst", W.SPHERE, 1e-6, 0, [W.Species("G", 0.0, 5000), W.Species("M", 1.0, 0)],
                 [W.unimol(0, -1, 1.0, placement=W.EMIT, p2=1, release=0.005)],
                 outer_radius_um=1.0, capacity=20000)
-    s = mabm.Sim(m)
-    s.step(1)
-    with pytest.raises(mabm.MabmError) as e:
-        s.counts()
-    assert e.value.code == mabm.E_CAPACITY
+    s = mabm.Sim(m, record=True)
+    G, _ = s.grid()
+    o = oracle.OracleSim(m, grid_n=G)
+    for k in range(3):
+        s.step(1)
+        o.step(1)
+        assert_same(s.export(), o.export(), f"burst t={k + 1}")
+    assert s.counts()[0].tolist() == [5000, 15000]
 
 
 def test_agent_updates_and_profile(mabm):
