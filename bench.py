@@ -280,17 +280,26 @@ def run_single(args, torch, mabm, W, model, steps: int, warmup: int, profile: bo
     return out, sim
 
 
-def late_sample(torch, sim, at_step: int, steps: int) -> dict:
+def late_sample(torch, sim, at_step: int, steps: int, kernels: bool = True) -> dict:
     """The rate of the same simulation later in its run: advanced to step
-    ``at_step`` (untimed), then ``steps`` timed steps."""
+    ``at_step`` (untimed), then ``steps`` timed steps, then (with
+    ``kernels``) the same number again with per-kernel durations."""
     _, t = sim.counts()
     if t < at_step:
         sim.step(at_step - t)
         sim.counts()
     ms, updates = timed_steps(torch, sim, steps)
     _, t1 = sim.counts()
-    return {"from_step": t1 - steps, "steps": steps, "value": updates / (ms / 1e3),
-            "ms_per_step": ms / steps}
+    out = {"from_step": t1 - steps, "steps": steps, "value": updates / (ms / 1e3),
+           "ms_per_step": ms / steps}
+    if kernels:
+        sim.profile(True)
+        timed_steps(torch, sim, steps)
+        prof = sim.profile_read()
+        sim.profile(False)
+        out["kernels_avg_us"] = {k: round(1e3 * tot / n, 3) for k, (n, tot) in prof.items() if n}
+        out["kernels_launches"] = {k: n for k, (n, tot) in prof.items() if n}
+    return out
 
 
 def _bits(e: dict) -> dict:

@@ -314,8 +314,9 @@ mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
  * not depend on them).  MABM_PARAM_PROPOSE_LANES: lanes per claimer, 4, 8,
  * 16 or 32 (0: the library's choice; raised to the least that covers the
  * stencil with two cells per lane).  MABM_PARAM_PROPOSE_MIN_WORKGROUPS: the
- * fewest workgroups the search launches, chunks of sorted agents being
- * shared by up to 16 workgroups to reach it (0: 2048).  Synchronises the
+ * fewest workgroups (of 256 threads, one per chunk of 1,024 sorted agents)
+ * the search launches, chunks being shared by up to 16 workgroups to reach
+ * it (0: 2048).  Synchronises the
  * stream; E_INVALID for an unknown parameter or value. */
 #define MABM_PARAM_PROPOSE_LANES 1
 #define MABM_PARAM_PROPOSE_MIN_WORKGROUPS 2

@@ -54,6 +54,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kPChunk = int(kClaimChunk);  // sorted agents per workgroup of propose
+constexpr int kPropBlock = kPChunk / 4;    // threads of a propose workgroup (four agents each)
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -499,7 +500,8 @@ __global__ void __launch_bounds__(kBlock) k_move(Dev d, int p, int record, int b
 // appends the children after the binned agents; a step that keeps the
 // binning first refills the holes listed since the binning, then appends.
 // ---------------------------------------------------------------------------
-static_assert(kBirthRun == kBlock, "one birth record per thread of a sorting workgroup");
+static_assert(kBirthRun == kBlock && kBirthRun <= kPropBlock,
+              "one birth record per thread of a sorting workgroup");
 
 __device__ __forceinline__ unsigned long long birth_key(const Birth& b)
 {
@@ -515,17 +517,21 @@ __device__ void sort_birth_runs(const Dev& d, int p, uint32_t w, uint32_t n_w)
     __shared__ unsigned long long key[kBirthRun];
     __shared__ uint32_t pos[kBirthRun];
     const uint32_t nb = min(d.ctl->n_births[p], d.capacity);
+    if (nb <= kBirthRun) return;  // a single run is ranked where it is placed
     const uint32_t j = threadIdx.x;
+    const bool act = j < kBirthRun;  // a wider workgroup's other threads only synchronise
     for (uint32_t run = w; run * kBirthRun < nb; run += n_w) {
         const uint32_t lo = run * kBirthRun;
         const uint32_t m = min(kBirthRun, nb - lo);
-        key[j] = j < m ? birth_key(d.births[lo + j]) : ~0ull;
-        pos[j] = j;
+        if (act) {
+            key[j] = j < m ? birth_key(d.births[lo + j]) : ~0ull;
+            pos[j] = j;
+        }
         __syncthreads();
         for (uint32_t k = 2; k <= kBirthRun; k <<= 1) {
             for (uint32_t h = k >> 1; h > 0; h >>= 1) {
                 const uint32_t l = j ^ h;
-                if (l > j) {
+                if (act && l > j) {
                     const bool up = (j & k) == 0;
                     const unsigned long long a = key[j], c = key[l];
                     if ((a > c) == up) {
@@ -539,7 +545,7 @@ __device__ void sort_birth_runs(const Dev& d, int p, uint32_t w, uint32_t n_w)
                 __syncthreads();
             }
         }
-        if (j < m) {
+        if (act && j < m) {
             const unsigned long long kj = key[j];
             d.bkey[lo + j] = kj;
             // first position of this record's simulation in the sorted run
@@ -585,30 +591,16 @@ __device__ __forceinline__ BirthSlots birth_slots(const Dev& d, const StepState&
     return BirthSlots{cur.n_slots, nb < avail ? nb : avail, cur.h_used};
 }
 
-// Places birth record k of the step (nb records; their runs sorted): its
-// rank by (simulation, parent id) gives its slot and its id.  The child
-// takes no part in its birth step's search (busy flag); while a binning is
-// kept it heads the extra chain of its cell, or, in a refilled hole that
-// already lies in a chain, joins the global list.
+// Writes birth record bb as the child of rank r among the step's children
+// (`smaller` of them belong to simulations of lower index): its slot and
+// id follow from the rank.  The child takes no part in its birth step's
+// search (busy flag); while a binning is kept it heads the extra chain of
+// its cell, or, in a refilled hole that already lies in a chain, joins the
+// global list.
 template <bool B>
-__device__ void place_birth(const Dev& d, int p, const Agents& A, uint32_t k, uint32_t nb, bool bin,
-                            const BirthSlots& bs, int record)
+__device__ void put_birth(const Dev& d, int p, const Agents& A, const Birth& bb, uint32_t r,
+                          uint32_t smaller, const BirthSlots& bs, int record)
 {
-    const Birth bb = d.births[k];
-    const unsigned long long key = birth_key(bb);
-    const uint2 br = d.brank[k];
-    uint32_t r = br.x, smaller = br.y;
-    const uint32_t runs = (nb + kBirthRun - 1) >> kBirthRunLog;
-    if (runs > 1) {
-        const uint32_t own = k >> kBirthRunLog;
-        for (uint32_t q = 0; q < runs; ++q) {
-            if (q == own) continue;
-            const unsigned long long* run = d.bkey + (size_t(q) << kBirthRunLog);
-            const uint32_t len = min(kBirthRun, nb - (q << kBirthRunLog));
-            r += count_below(run, len, key);
-            if (B) smaller += count_below(run, len, key & 0xFFFFFFFF00000000ull);
-        }
-    }
     const uint32_t sim = B ? bb.sp >> kMetaSimShift : 0u;
     const uint32_t j = r < bs.m ? d.hlist[(bs.h_used + r) % d.slots] : bs.base + (r - bs.m);
     if (j >= d.slots) return;  // the bookkeeping reports the overflow
@@ -635,6 +627,71 @@ __device__ void place_birth(const Dev& d, int p, const Agents& A, uint32_t k, ui
             }
         }
     }
+}
+
+// Places birth record k of a step with more than one run of children
+// (their runs sorted): its rank is its rank in its run plus its lower bound
+// in every other run.
+template <bool B>
+__device__ void place_birth(const Dev& d, int p, const Agents& A, uint32_t k, uint32_t nb,
+                            const BirthSlots& bs, int record)
+{
+    const Birth bb = d.births[k];
+    const unsigned long long key = birth_key(bb);
+    const uint2 br = d.brank[k];
+    uint32_t r = br.x, smaller = br.y;
+    const uint32_t runs = (nb + kBirthRun - 1) >> kBirthRunLog;
+    const uint32_t own = k >> kBirthRunLog;
+    for (uint32_t q = 0; q < runs; ++q) {
+        if (q == own) continue;
+        const unsigned long long* run = d.bkey + (size_t(q) << kBirthRunLog);
+        const uint32_t len = min(kBirthRun, nb - (q << kBirthRunLog));
+        r += count_below(run, len, key);
+        if (B) smaller += count_below(run, len, key & 0xFFFFFFFF00000000ull);
+    }
+    put_birth<B>(d, p, A, bb, r, smaller, bs, record);
+}
+
+// Places the children of a step with at most one run of them, all by one
+// workgroup: their keys in LDS, each child's rank by counting the keys below
+// its own.
+template <bool B>
+__device__ void place_births_small(const Dev& d, int p, const Agents& A, uint32_t nb,
+                                   const BirthSlots& bs, int record)
+{
+    __shared__ unsigned long long skey[kBirthRun];
+    const uint32_t j = threadIdx.x;
+    Birth bb{};
+    if (j < nb) {
+        bb = d.births[j];
+        skey[j] = birth_key(bb);
+    }
+    __syncthreads();
+    if (j < nb) {
+        const unsigned long long key = skey[j], first = key & 0xFFFFFFFF00000000ull;
+        uint32_t r = 0, smaller = 0;
+        for (uint32_t q = 0; q < nb; ++q) {
+            const unsigned long long o = skey[q];
+            r += o < key ? 1u : 0u;
+            smaller += o < first ? 1u : 0u;
+        }
+        put_birth<B>(d, p, A, bb, r, smaller, bs, record);
+    }
+}
+
+// All of a step's children, placed by workgroup w of n_w: one run of
+// children by the workgroup `small_w`, more by all of them.
+template <bool B>
+__device__ void place_births(const Dev& d, int p, const Agents& A, uint32_t nb,
+                             const BirthSlots& bs, int record, uint32_t w, uint32_t n_w,
+                             uint32_t small_w)
+{
+    if (nb <= kBirthRun) {
+        if (w == small_w && nb) place_births_small<B>(d, p, A, nb, bs, record);
+        return;
+    }
+    for (uint32_t k = w * kBlock + threadIdx.x; k < nb; k += n_w * kBlock)
+        place_birth<B>(d, p, A, k, nb, bs, record);
 }
 
 // The step's bookkeeping (O9, O10), run by one whole workgroup while the
@@ -715,8 +772,7 @@ __device__ void scatter_births(const Dev& d, int p, int record, uint32_t w, uint
 {
     const uint32_t nb = min(d.ctl->n_births[p], d.capacity);
     const BirthSlots bs = birth_slots(d, d.ctl->s[p], true, nb);
-    for (uint32_t k = w * kBlock + threadIdx.x; k < nb; k += n_w * kBlock)
-        place_birth<B>(d, p, d.a[p ^ 1], k, nb, true, bs, record);
+    place_births<B>(d, p, d.a[p ^ 1], nb, bs, record, w, n_w, 0u);
     if (w == n_w - 1) {
         // the scan has read this parity's tile sums (and cleared the
         // other's): clear them too, so that steps keeping this binning need
@@ -899,7 +955,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record, ui
 }
 
 // Compact, in LDS, the claimers of this workgroup's chunk [first, last) of
-// kPChunk = kClaimPer x kBlock sorted agents: each thread reads the claimer
+// kPChunk = kClaimPer x kPropBlock sorted agents: each thread reads the claimer
 // flags of its kClaimPer agents as one word (1: a claimer, 2: a claimer that
 // searches the 27-cell stencil this step), a wave-level prefix of both
 // counts places them within the wave, and the waves' totals, exchanged
@@ -909,7 +965,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Dev d, int p, int record, ui
 // caller before anything else so that its latency overlaps the kernel's
 // other set-up loads.  Returns the list length, and the wide claimers'
 // count in *n_wide.
-constexpr int kClaimPer = kPChunk / kBlock;
+constexpr int kClaimPer = kPChunk / kPropBlock;
 constexpr uint32_t kPropLds = 256;  // proposals a workgroup stages in LDS
 static_assert(kClaimPer == 2 || kClaimPer == 4, "two or four claimer flags per thread");
 using FlagWord = std::conditional_t<kClaimPer == 4, uint32_t, uint16_t>;
@@ -940,13 +996,13 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
         const uint32_t u = __shfl_up(incl, o, 64);
         if (lane >= o) incl += u;
     }
-    __shared__ uint32_t wsum[kBlock / 64];
+    __shared__ uint32_t wsum[kPropBlock / 64];
     const int wv = int(threadIdx.x) >> 6;
     if (lane == 63) wsum[wv] = incl;
     __syncthreads();
     uint32_t base = incl - mine, total = 0;
 #pragma unroll
-    for (int k = 0; k < kBlock / 64; ++k) {
+    for (int k = 0; k < kPropBlock / 64; ++k) {
         if (k < wv) base += wsum[k];
         total += wsum[k];
     }
@@ -970,7 +1026,7 @@ __device__ __forceinline__ uint32_t compact_claimers(uint32_t word, uint32_t fir
 // propose (O7): for each claimer, the eligible partner minimising (d^2, id)
 // over its 8-cell or 27-cell stencil, then a Bernoulli draw,
 // then the handshake key into both claim slots by atomic minimum.  A
-// workgroup takes 1024 sorted agents; their claimers are searched by
+// workgroup takes 1,024 sorted agents; their claimers are searched by
 // subgroups of 4 (or 16) lanes, two stencil cells per lane, and the lanes'
 // best candidates are reduced by shuffles, so each claimer's dependent
 // chain of loads is a few round trips long.
@@ -1183,8 +1239,9 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
 }
 
 template <bool B>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
-k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search_blocks)
+__global__ void __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search_blocks,
+          uint32_t core_blocks)
 {
     __shared__ uint32_t list[kPChunk];
     __shared__ uint4 plocal[kPropLds];
@@ -1200,7 +1257,10 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search
     // `split` workgroups share a chunk (small simulations, whose few chunks
     // would otherwise leave the claimers to a few workgroups): each compacts
     // the chunk and searches every split-th pass of its claimers
-    const uint32_t g = xcd_chunk(search_blocks);
+    // the chunks within the capacity are dealt to the XCDs; the chunks of
+    // the slot headroom (holes beyond the capacity, rarely in use) come
+    // last in dispatch order
+    const uint32_t g = blockIdx.x < core_blocks ? xcd_chunk(core_blocks) : blockIdx.x;
     const uint32_t share = g % split;
     const uint32_t first = g / split * kPChunk;
     // The thread's four claimer flags, requested first.  The flag array is
@@ -1220,9 +1280,9 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search
         const uint32_t nw = uint32_t(T.ns) * (kMaxSpecies / 4);
         const uint32_t* src = reinterpret_cast<const uint32_t*>(&T.rule_of[0][0]);
         uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
-        for (uint32_t q = threadIdx.x; q < nw; q += kBlock) dst[q] = src[q];
-        for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kBlock) P.r2[q] = T.rule[q].r2;
-        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kBlock) {
+        for (uint32_t q = threadIdx.x; q < nw; q += kPropBlock) dst[q] = src[q];
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kPropBlock) P.r2[q] = T.rule[q].r2;
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kPropBlock) {
             P.r2max[q] = T.claim_r2max[q];
             P.rmax[q] = T.claim_rmax[q];
             P.dmax[q] = T.claim_dmax[q];
@@ -1249,7 +1309,7 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search
     const uint32_t narrow = d.prop_lanes > wmin ? d.prop_lanes : wmin;
     const uint32_t wide = narrow > 16u ? narrow : 16u;
     const uint32_t lanes = nw * wide + (nl - nw) * narrow;
-    for (uint32_t v = share * kBlock + threadIdx.x; v - threadIdx.x < lanes; v += kBlock * split) {
+    for (uint32_t v = share * kPropBlock + threadIdx.x; v - threadIdx.x < lanes; v += kPropBlock * split) {
         if (v >= lanes) continue;
         uint32_t q, width;
         const bool is_wide = v < nw * wide;
@@ -1280,7 +1340,7 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search
     if (np == 0) return;
     if (threadIdx.x == 0) pbase = atomicAdd(&d.ctl->n_prop[p], np);
     __syncthreads();
-    for (uint32_t q = threadIdx.x; q < np; q += kBlock) d.plist[pbase + q] = plocal[q];
+    for (uint32_t q = threadIdx.x; q < np; q += kPropBlock) d.plist[pbase + q] = plocal[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -1298,6 +1358,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     __shared__ uint32_t s_dead;
     const Tables& T = *d.tab;
     Ctl* ctl = d.ctl;
+    const uint32_t prop_blocks = gridDim.x - 1;  // the last workgroup keeps the books
     // the thread's first proposer entry is requested with the list's length
     // (entries past it are stale but inside the list's capacity)
     uint32_t q = blockIdx.x * kBlock + threadIdx.x;
@@ -1305,17 +1366,18 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
     if (!bin) {
+        // a step that keeps the binning places its children here (a few by
+        // the last workgroup, many by all) and does its bookkeeping
         const uint32_t nb = min(ctl->n_births[p], d.capacity);
         const BirthSlots bs = birth_slots(d, ctl->s[p], false, nb);
-        for (uint32_t k = q; k < nb; k += gridDim.x * kBlock)
-            place_birth<B>(d, p, d.a[p ^ 1], k, nb, false, bs, record);
-        if (blockIdx.x == 0) bookkeeping<B>(d, p, false);
+        place_births<B>(d, p, d.a[p ^ 1], nb, bs, record, blockIdx.x, gridDim.x, prop_blocks);
+        if (blockIdx.x == prop_blocks) bookkeeping<B>(d, p, false);
     }
-    if (blockIdx.x * kBlock >= np) return;
+    if (blockIdx.x == prop_blocks || blockIdx.x * kBlock >= np) return;
     if (threadIdx.x == 0) s_dead = 0;
     __syncthreads();
     const Agents A = d.a[p ^ 1];
-    for (; q < np; q += gridDim.x * kBlock) {
+    for (; q < np; q += prop_blocks * kBlock) {
         if (q >= blockIdx.x * kBlock + kBlock) e = d.plist[q];
         const uint32_t j = e.x, b = e.y, ida = e.z;
         const int rule = int(e.w & 0xFFu);
@@ -1562,16 +1624,19 @@ void launch_propose(const Dev& d, int p, int bin, uint32_t moved, hipStream_t s,
     while (split < 16 && chunks * split * 2 <= min_blocks) split *= 2;
     // a step that keeps the binning sorts its birth runs in extra workgroups
     const unsigned search = chunks * split;
+    const unsigned core = chunks_for(d.capacity) * split;
     const unsigned grid = search + (bin ? 0u : d.birth_blocks);
-    if (d.n_sims > 1) go(k_propose<true>, grid, kBlock, s, ev, d, p, split, bin, moved, search);
-    else go(k_propose<false>, grid, kBlock, s, ev, d, p, split, bin, moved, search);
+    if (d.n_sims > 1)
+        go(k_propose<true>, grid, kPropBlock, s, ev, d, p, split, bin, moved, search, core);
+    else go(k_propose<false>, grid, kPropBlock, s, ev, d, p, split, bin, moved, search, core);
 }
 void launch_finish(const Dev& d, int p, int record, int bin, hipStream_t s, const KEvents& ev)
 {
     // a fixed grid strides over the step's proposer list (and a kept step's
-    // children)
+    // children), and one more workgroup keeps the books
     unsigned nb = blocks_for(d.capacity);
     if (nb > kFinishBlocks) nb = kFinishBlocks;
+    nb += 1;
     if (d.n_sims > 1) go(k_finish<true>, nb, kBlock, s, ev, d, p, record, bin);
     else go(k_finish<false>, nb, kBlock, s, ev, d, p, record, bin);
 }

@@ -5,8 +5,11 @@ unimolecular events and confirmed partners are compared for every live
 agent, id-keyed, at several checkpoints; species counts and the step
 counter are compared too.  Sizes: the C1 workload at full size and horizon,
 scaled C2/C3 models that the oracle finishes in seconds while spanning many
-cells and a ragged tail, and the full 2M-agent C2 and 5M-agent C3 for 20
-steps in the launch configuration the benchmark times.
+cells and a ragged tail (the scaled C3 to 2,000 steps, where translocated
+agents crowd the nuclear membrane and births have refilled many holes), and
+the full 2M-agent C2 and 5M-agent C3 for 20 steps in the launch
+configuration the benchmark times, then again recording cell ids, events
+and partners for the comparison at step 20.
 """
 import numpy as np
 import pytest
@@ -42,18 +45,19 @@ def test_c2_scaled():
 
 def test_c3_scaled_births_and_translocation():
     m = W.c3(20_000, seed=12, n_genes=300)
-    run_pair(m, [1, 10, 100, 300])
+    run_pair(m, [1, 10, 100, 300, 800, 2000])
 
 
 def test_c2_full_size_in_bench_configuration():
     # the benchmark's configuration: 2M agents, no recording, library-chosen grid
     run_pair(W.c2(), [1, 3, 20], record=False)
-    run_pair(W.c2(), [2], record=True)
+    run_pair(W.c2(), [20], record=True)
 
 
 def test_c3_full_size_twenty_steps():
     # 5M agents in nested compartments with births, at full size
     run_pair(W.c3(), [1, 20], record=False)
+    run_pair(W.c3(), [20], record=True)
 
 
 def test_ragged_and_tiny_sizes():
