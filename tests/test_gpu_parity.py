@@ -270,3 +270,64 @@ def test_largest_grid_matches_oracle():
     assert g.grid()[0] == 512
     g.close()
     run_pair(m, [1, 3, 6], cell_um=0.01054)
+
+
+@pytest.mark.parametrize("bin_max", [0, 1])
+def test_crowded_stencils_searched_by_whole_waves(bin_max):
+    # cells far larger than the contact radius in a dense box: every
+    # claimer's stencil lists hundreds of candidates, so the search deals
+    # them over a whole wave; with and without kept binnings (splits place
+    # agents in extra chains), against the oracle
+    import paper_2606_14603_amd as mabm
+    m = W.c1(n_a=9000, n_b=9000, n_c=2000, box_um=0.9, seed=31, unbind_p=0.02)
+    g = mabm.Sim(m, record=True, cell_um=0.15)
+    g.set_param(mabm.PARAM_BIN_EVERY_MAX, bin_max)
+    G, _ = g.grid()
+    say(f"[crowded] {m.n_agents} agents, grid {G}, {m.n_agents / G ** 3:.0f} per cell, "
+        f"bin_every {g.get_param(mabm.PARAM_BIN_EVERY)}")
+    o = oracle.OracleSim(m, grid_n=G)
+    done = 0
+    for c in (1, 2, 5, 12, 30):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        assert_same(g.export(), o.export(), f"crowded t={c}")
+
+
+def test_crowded_stencils_in_a_batch():
+    import paper_2606_14603_amd as mabm
+    models = [W.c1(n_a=n, n_b=n, n_c=n // 5, box_um=0.9 * (n / 9000) ** (1 / 3), seed=40 + k,
+                   unbind_p=0.02).with_(cell_um=0.15 * (n / 9000) ** (1 / 3), name=f"crowd{k}")
+              for k, n in enumerate([9000, 3000, 6000])]
+    b = mabm.Batch(models, record=True)
+    orcs = [oracle.OracleSim(m, grid_n=b.grid(k)[0]) for k, m in enumerate(models)]
+    done = 0
+    for c in (1, 6, 20):
+        b.step(c - done)
+        for o in orcs:
+            o.step(c - done)
+        done = c
+        for k, o in enumerate(orcs):
+            assert_same(b.export(k), o.export(), f"{models[k].name} t={c}")
+
+
+def test_crowded_wide_stencils_in_kept_steps():
+    # a contact radius above half the cell size forces the 27-cell stencil
+    # on every claimer, and a dense box makes every stencil crowded, so
+    # claimers are searched over 27 cells by a whole wave, in binning and
+    # kept steps
+    import paper_2606_14603_amd as mabm
+    m = W.c1(n_a=9000, n_b=9000, n_c=2000, box_um=0.9, seed=33, unbind_p=0.02,
+             radius_um=0.08, release_um=0.04)
+    g = mabm.Sim(m, record=True, cell_um=0.13)  # 6 cells of 150 nm < 2.02 x 80 nm
+    G, _ = g.grid()
+    every = g.get_param(mabm.PARAM_BIN_EVERY)
+    say(f"[crowded wide] grid {G}, bin_every {every}")
+    assert G == 6 and every >= 3
+    o = oracle.OracleSim(m, grid_n=G)
+    done = 0
+    for c in (1, 3, 7, 16):
+        g.step(c - done)
+        o.step(c - done)
+        done = c
+        assert_same(g.export(), o.export(), f"crowded wide t={c}")
