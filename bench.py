@@ -112,10 +112,10 @@ LANE_OP_PEAK = 256 * 64 * 2.4e9
 # same counters read for the 512 MiB device copy in that run (FETCH x2.0,
 # WRITE x1.0).  Valid only for the kernel sources it was taken on (SHA-256
 # of the three files below); reported as null otherwise.
-TRAFFIC = {"fetch_scale": 2.0, "write_scale": 1.0,
-           "sources_sha256": "42097d79359f869332d6888b7d7987146581af4f1135c3104f43067129259ec6",
+TRAFFIC = {"fetch_scale": 2.000, "write_scale": 1.000,
+           "sources_sha256": "4388d51374a62e58b02337f2dbf1db89b57d7d2141ff35d051d49ed6b6e697b0",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19629.7, 40071.2), "scan": (4631.8, 16416.1), "scatter": (34501.1, 56197.2), "propose": (17828.8, 2951.4), "finish": (152.5, 0.5)}}
+           "kib": {"move": (19624.0, 40071.2), "scan": (4636.2, 16416.1), "scatter": (34455.6, 56195.2), "propose": (17713.6, 2952.5), "finish": (172.9, 0.5)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
