@@ -44,6 +44,11 @@ extern "C" {
 #define MABM_ABI_VERSION 1u
 #define MABM_MAX_SPECIES 64
 #define MABM_MAX_RULES 255
+/* Cells per axis of the spatial hash, at most (a finer cell_um is coarsened
+ * to it); the grids of one handle's simulations hold at most 2^31 cells
+ * together, counted at the power of two at or above each grid (else
+ * E_INVALID, and mabm_arena_bytes returns 0). */
+#define MABM_MAX_GRID 1024
 #define MABM_NONE 0xFFFFFFFFu
 
 typedef enum {
@@ -84,7 +89,8 @@ typedef struct {
     float dt_s;            /* time step, s (> 0) */
     uint64_t seed;         /* Philox key */
     uint32_t capacity;     /* maximum live agents at any step end (see below) */
-    float cell_um;         /* spatial-hash cell size, um; 0 = chosen by the library */
+    float cell_um;         /* spatial-hash cell size, um; 0 = chosen by the library;
+                              at most MABM_MAX_GRID cells per axis */
     uint32_t flags;        /* MABM_FLAG_* */
 } mabm_config;
 

@@ -33,6 +33,7 @@ PARAM_PROPOSE_LANES = 1
 PARAM_PROPOSE_MIN_WORKGROUPS = 2
 PARAM_BIN_EVERY_MAX = 3
 PARAM_BIN_EVERY = 4
+MAX_GRID = 1024  # cells per axis of the spatial hash, at most
 
 
 class MabmError(RuntimeError):

@@ -38,7 +38,11 @@ float extent_of(const mabm_config& c)
     return c.geometry == MABM_PERIODIC_BOX ? c.box_um : c.outer_radius_um * 2.0f;
 }
 
-constexpr uint32_t kMaxGrid = 512;  // cells per axis
+constexpr uint32_t kMaxGrid = MABM_MAX_GRID;  // cells per axis (10-bit Morton coordinates)
+// cells of all simulations together: cell keys, cell-table indices and the
+// counting sort's prefix sums are 32-bit words
+constexpr uint64_t kMaxCells = 1ull << 31;
+static_assert(kMaxGrid <= 1024, "Morton keys interleave 10-bit cell coordinates");
 
 // cells per axis implied by the configuration alone: the requested cell
 // size, or the power of two nearest (in log) to one cell per agent of
@@ -758,6 +762,12 @@ bool batch_ok(const mabm_config* cs, uint32_t n, std::string& why)
     }
     if (total_capacity(cs, n) > (1ull << 30)) {
         why = "summed capacity of the batch above 2^30";
+        return false;
+    }
+    uint64_t cells = 0;
+    for (uint32_t k = 0; k < n; ++k) cells += (uint64_t)1 << (3 * morton_bits(grid_from_config(cs[k])));
+    if (cells > kMaxCells) {
+        why = "cell grids above 2^31 cells together (a larger cell_um gives fewer)";
         return false;
     }
     return true;

@@ -60,9 +60,10 @@ def candidates(m) -> List[float]:
     the finest cell the 8-cell stencil allows."""
     ext, rmax = _extent(m), _rmax(m)
     g0 = 2 ** round(math.log2(max(3.0, (max(1, m.capacity)) ** (1.0 / 3.0))))
-    grids = {max(3, g0 // 4), max(3, g0 // 2), g0, min(512, 2 * g0)}
+    from . import MAX_GRID
+    grids = {max(3, g0 // 4), max(3, g0 // 2), g0, min(MAX_GRID, 2 * g0)}
     if rmax > 0:
-        grids.add(max(3, min(512, int(ext / (2.02 * rmax)))))
+        grids.add(max(3, min(MAX_GRID, int(ext / (2.02 * rmax)))))
     out = []
     for g in sorted(grids):
         h = ext / g
@@ -165,11 +166,12 @@ class BatchTuneResult:
 def batch_cell(m, agents_per_cell: float) -> float:
     """Cell size giving about ``agents_per_cell`` agents per cell over the
     simulation's volume (0: the library's default), kept at or above the
-    largest contact radius and within the 512-cell grid."""
+    largest contact radius and within the largest grid."""
     if agents_per_cell <= 0 or m.n_agents == 0:
         return 0.0
     h = (_volume(m) * agents_per_cell / m.n_agents) ** (1.0 / 3.0)
-    h = max(h, 1.01 * _rmax(m), _extent(m) / 512.0)
+    from . import MAX_GRID
+    h = max(h, 1.01 * _rmax(m), _extent(m) / MAX_GRID)
     return h * (1.0 + 1e-6)
 
 

@@ -259,17 +259,51 @@ def test_largest_tables_match_oracle():
     run_pair(m, [1, 2, 5, 20, 40])
 
 
-def test_largest_grid_matches_oracle():
-    # 512 cells per axis, the library's largest grid: 27-bit Morton keys and
-    # scan tiles of 2^6 passes (134M cells in at most 1,024 tiles)
-    # (20k cascade agents in a 2.7 um sphere: 10.5 nm cells, just above the
-    # largest contact radius)
+@pytest.mark.parametrize("radius_um,grid", [(2.7, 512), (5.4, 1024)])
+def test_largest_grids_match_oracle(radius_um, grid):
+    # 512 cells per axis (27-bit Morton keys, scan tiles of 2^6 passes: 134M
+    # cells in at most 1,024 tiles) and 1,024, the library's largest grid
+    # (30-bit keys, tiles of 2^9 passes: 2^30 cells, 12.9 GB of cell tables)
+    # (20k cascade agents in a sphere: 10.5 nm cells, just above the largest
+    # contact radius)
     import paper_2606_14603_amd as mabm
-    m = W.c2(20_000, seed=8, steps=6).with_(outer_radius_um=2.7)
+    m = W.c2(20_000, seed=8, steps=6).with_(outer_radius_um=radius_um)
     g = mabm.Sim(m, record=True, cell_um=0.01054)
-    assert g.grid()[0] == 512
+    assert g.grid()[0] == grid == min(grid, mabm.MAX_GRID)
     g.close()
     run_pair(m, [1, 3, 6], cell_um=0.01054)
+
+
+def test_beyond_2_28_slots_matches_oracle():
+    # 272M nuclear-signalling agents, more than 2^28, so the records in use
+    # reach past 4 GiB and agent-indexed byte addresses need more than 32
+    # bits, on the 1,023-cell grid; two steps with translocations and
+    # births; the state digest and counts against the oracle's (comparing
+    # the full export would take minutes)
+    import torch
+    import paper_2606_14603_amd as mabm
+    from parity import state_digest
+    m = W.c3(272_000_000)
+    g = mabm.Sim(m, cell_um=2 * m.outer_radius_um / 1024 * (1 + 1e-6))
+    g.step(2)
+    gd, (gc, gt) = int(g.digest()[0]), g.counts()
+    say(f"[big] {m.n_agents} agents, grid {g.grid()[0]}, gpu digest {gd:#x}")
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    oracle.threads(16)
+    o = oracle.OracleSim(m)
+    o.step(1)
+    say("[big] oracle step 1")
+    o.step(1)
+    oc, ot = o.counts()
+    e = o.export()
+    o.close()
+    od, n = 0, len(e["id"])
+    for a in range(0, n, 20_000_000):
+        od = (od + state_digest({k: v[a:a + 20_000_000] for k, v in e.items()})) % (1 << 64)
+    assert gt == ot == 2 and np.array_equal(gc, oc)
+    assert gd == od, (hex(gd), hex(od))
 
 
 @pytest.mark.parametrize("bin_max", [0, 1])

@@ -125,5 +125,9 @@ def test_tuner_candidates_respect_the_contact_radius():
     assert all(h >= 1.01 * 0.010 for h in c)
     # the finest 8-cell-stencil grid: h >= 2.02 x 10 nm
     assert int(ext / (2.02 * 0.010)) in grids or 512 in grids
+    # a 300M-agent cascade (a 53 um sphere) also tries the largest grid
+    mb = W.c2(300_000_000)
+    big = sorted(round(2 * mb.outer_radius_um / h) for h in tune.candidates(mb))
+    assert big[-1] == 1024 and 512 in big
     assert tune.shape_key(m) == tune.shape_key(W.c2(2_000_000, seed=5))
     assert tune.shape_key(m) != tune.shape_key(W.c2(200_000))
