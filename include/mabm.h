@@ -338,6 +338,17 @@ mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
 /* MABM_PARAM_BIN_EVERY (mabm_get_param only): steps between binnings in
  * effect (finalizes the model). */
 #define MABM_PARAM_BIN_EVERY 4
+/* MABM_PARAM_PROPOSE_MODE: how the neighbour search finds the claimers
+ * (results do not depend on it).  1: per chunk of 1,024 agents in cell
+ * order, a workgroup searching the chunk's claimers with 4 lanes each (16
+ * for the 27-cell stencil).  2: over a list of the step's claimers, built by
+ * the kernel that flags them, every claimer getting 16 to 64 lanes as the
+ * list's length allows and a stencil cell's candidates shared by several of
+ * them (for sparse claimers in crowded cells); single simulations only
+ * (E_INVALID for a batch).  0 (default): 2 when the claimer species hold
+ * under 1/64 of the initial agents of a single simulation, else 1.
+ * mabm_get_param returns the mode in use, 1 or 2 (finalizes the model). */
+#define MABM_PARAM_PROPOSE_MODE 5
 mabm_status mabm_set_param(mabm_sim* sim, int32_t param, uint32_t value);
 mabm_status mabm_get_param(mabm_sim* sim, int32_t param, uint32_t* value);
 

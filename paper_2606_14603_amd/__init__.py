@@ -33,6 +33,7 @@ PARAM_PROPOSE_LANES = 1
 PARAM_PROPOSE_MIN_WORKGROUPS = 2
 PARAM_BIN_EVERY_MAX = 3
 PARAM_BIN_EVERY = 4
+PARAM_PROPOSE_MODE = 5  # 0 auto, 1 per chunk, 2 claimer list
 MAX_GRID = 1024  # cells per axis of the spatial hash, at most
 
 
@@ -264,7 +265,7 @@ class Sim:
 
     def set_param(self, param: int, value: int):
         """Performance parameter (PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS,
-        PARAM_BIN_EVERY_MAX); results do not depend on them."""
+        PARAM_BIN_EVERY_MAX, PARAM_PROPOSE_MODE); results do not depend on them."""
         self._chk(lib().mabm_set_param(self._h, int(param), int(value)))
 
     def get_param(self, param: int) -> int:

@@ -95,7 +95,8 @@ struct Layout {
     size_t ctl, tab, rec[2], id[2], rank, event, sclaim, cell_count, cell_start, tile_acc, slot,
         prop, plist, rkey, revent, rpartner, births, bkey, brank, hlist, counts, digest, simc,
         head, nxt, glob, total;
-    uint32_t ncells, ntiles, tile_shift;
+    uint32_t ncells, ntiles, tile_shift, clist_cap;
+    size_t clist, ccount;
     uint32_t capacity, slots;
 };
 
@@ -165,6 +166,12 @@ Layout make_layout(const mabm_config* cs, uint32_t n)
     L.head = take((padded + 1) * 4);
     L.nxt = take(cap * 4);
     L.glob = take(cap * 4);
+    // claimer list: each region takes the claimers of every kListRegions-th
+    // workgroup of move or scatter (one agent slot per thread)
+    const size_t wgs = (cap + 255) / 256;
+    L.clist_cap = (uint32_t)((wgs + kListRegions - 1) / kListRegions * 256);
+    L.clist = take((size_t)kListRegions * L.clist_cap * 4);
+    L.ccount = take((size_t)kListRegions * kListStride * 4);
     L.total = off;
     return L;
 }
@@ -216,6 +223,7 @@ struct mabm_sim {
     // (1: every step); `buf` is the agent buffer holding the current state,
     // `kept` the steps since the last binning (bin_every - 1 forces one)
     uint32_t bin_every = 1, bin_every_max = 0, kept = 0;
+    uint32_t propose_mode = 0;  // MABM_PARAM_PROPOSE_MODE as set (0: auto)
     int buf = 0;
     uint32_t G = 0;
     float h = 0.0f;
@@ -310,6 +318,8 @@ void timed(mabm_sim* s, int kid, F&& launch)
 // their new positions (or, placed twice, a global list), which the search
 // reads too.  Models without pair rules bin every step (nothing searches).
 constexpr uint32_t kMaxBinEvery = 8;
+constexpr uint32_t kModeChunks = 1, kModeList = 2;  // MABM_PARAM_PROPOSE_MODE values
+constexpr uint32_t kListBlocks = 2048;              // workgroups of the claimer-list search
 constexpr double kNormalBound = 5.78;
 
 // whether the model allows keeping cell lists at all: it has pair rules
@@ -618,6 +628,37 @@ void fill_dev(mabm_sim* s)
     d.capacity = L.capacity;
     d.slots = L.slots;
     d.n_sims = s->n_sims;
+    d.clist = (uint32_t*)(A + L.clist);
+    d.ccount = (uint32_t*)(A + L.ccount);
+    d.clist_cap = L.clist_cap;
+}
+
+// The neighbour search's mode (results do not depend on it): per chunk of
+// sorted agents, or over the claimer list (single simulations only).  The
+// list pays one atomic per wave that holds claimers when it is built, and
+// spreads few claimers in crowded cells over whole waves, so `auto` takes
+// it when claimers are under 1/64 of the initial agents.
+void set_list_mode(mabm_sim* s)
+{
+    Dev& d = s->dev;
+    bool list = false;
+    if (s->n_sims == 1 && s->propose_mode != kModeChunks) {
+        if (s->propose_mode == kModeList) {
+            list = true;
+        } else {
+            const Tables& T = s->tabs[0];
+            uint64_t claimers = 0, all = 0;
+            for (int k = 0; k < T.ns; ++k) {
+                const uint32_t c = T.init_end[k] - (k ? T.init_end[k - 1] : 0u);
+                all += c;
+                if (T.claimer[k]) claimers += c;
+            }
+            list = claimers > 0 && claimers * 64 < all;
+        }
+    }
+    d.list_mode = list ? 1u : 0u;
+    const uint32_t wgs = (d.capacity + 255u) / 256u;
+    d.list_blocks = wgs < kListBlocks ? wgs : kListBlocks;
 }
 
 // first step / query / import: tables, hash geometry, upload, placement
@@ -671,6 +712,9 @@ mabm_status finalize(mabm_sim* s, bool place)
     HIP_OK(s, hipMemsetAsync(d.tile_acc, 0, (size_t)2 * d.ntiles * kTileStride * 4, s->stream));
     // claim slots are all-ones between steps (each step resets those it used)
     HIP_OK(s, hipMemsetAsync(d.slot, 0xFF, (size_t)d.slots * 8, s->stream));
+    // the claimer list starts empty (each step's finish empties it again)
+    HIP_OK(s, hipMemsetAsync(d.ccount, 0, (size_t)kListRegions * kListStride * 4, s->stream));
+    set_list_mode(s);
     launch_fill_records(d, s->stream);
     if (place)
         for (uint32_t k = 0; k < s->n_sims; ++k) {
@@ -1442,6 +1486,13 @@ mabm_status mabm_set_param(mabm_sim* s, int32_t param, uint32_t value)
         if (value > (1u << 20)) return fail(s, MABM_E_INVALID, "at most 2^20 workgroups");
         s->dev.prop_min_blocks = value;
         return MABM_OK;
+    case MABM_PARAM_PROPOSE_MODE:
+        if (value > kModeList) return fail(s, MABM_E_INVALID, "search mode must be 0, 1 or 2");
+        if (value == kModeList && s->n_sims > 1)
+            return fail(s, MABM_E_INVALID, "the claimer-list search serves single simulations");
+        s->propose_mode = value;
+        if (s->finalized) set_list_mode(s);
+        return MABM_OK;
     case MABM_PARAM_BIN_EVERY_MAX:
         if (value > kMaxBinEvery) return fail(s, MABM_E_INVALID, "at most 8 steps between binnings");
         s->bin_every_max = value;
@@ -1459,6 +1510,13 @@ mabm_status mabm_get_param(mabm_sim* s, int32_t param, uint32_t* value)
     case MABM_PARAM_PROPOSE_LANES: *value = s->dev.prop_lanes; return MABM_OK;
     case MABM_PARAM_PROPOSE_MIN_WORKGROUPS: *value = s->dev.prop_min_blocks; return MABM_OK;
     case MABM_PARAM_BIN_EVERY_MAX: *value = s->bin_every_max; return MABM_OK;
+    case MABM_PARAM_PROPOSE_MODE: {
+        // the mode in use (1 or 2), once the model is final
+        mabm_status st = finalize(s, true);
+        if (st != MABM_OK) return st;
+        *value = s->dev.list_mode ? kModeList : kModeChunks;
+        return MABM_OK;
+    }
     case MABM_PARAM_BIN_EVERY: {
         mabm_status st = finalize(s, true);
         if (st != MABM_OK) return st;

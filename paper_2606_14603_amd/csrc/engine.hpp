@@ -36,6 +36,16 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kEnd = 0x7FFFFFFFu;
 constexpr uint32_t kUnlinked = 0x7FFFFFFEu;
 constexpr uint32_t kGlobBit = 0x80000000u;
+
+// Claimer list (the search mode for sparse claimers): the step's claimers,
+// appended by the kernel that flags them (scatter in a binning step, move in
+// a step that keeps the binning) into kListRegions regions, each with its
+// own counter on its own 128-byte line (a workgroup appends to region
+// blockIdx mod kListRegions, one atomic per wave); an entry is the
+// claimer's slot, with kListWide set when it searches the 27-cell stencil.
+constexpr uint32_t kListRegions = 64;
+constexpr uint32_t kListStride = 32;  // words between region counters
+constexpr uint32_t kListWide = 0x80000000u;
 // Births of a step are ranked by (simulation, parent id): runs of kBirthRun
 // records are sorted in LDS by kBirthSortBlocks workgroups, and each birth's
 // rank is its rank in its own run plus its lower bound in every other run.
@@ -215,6 +225,14 @@ struct Dev {
     // not depend on them): lanes per claimer (0: 4 for the 8-cell stencil,
     // 16 for the 27-cell one) and the fewest workgroups to launch
     uint32_t prop_lanes, prop_min_blocks;
+    // claimer list: list_mode set (single simulations only) when the search
+    // runs over the listed claimers instead of per chunk of sorted agents;
+    // clist holds kListRegions regions of clist_cap entries, ccount their
+    // counters (zeroed by finish for the next step); list_blocks workgroups
+    // search
+    uint32_t* clist;
+    uint32_t* ccount;
+    uint32_t clist_cap, list_mode, list_blocks;
 };
 
 // kernel indices for per-kernel timing

@@ -272,6 +272,18 @@ __device__ __forceinline__ void list_hole(const Dev& d, uint32_t i)
     d.hlist[k % d.slots] = i;
 }
 
+// A claimer of this step, from the lanes that take this branch, joins the
+// claimer list (single simulations in list mode): region blockIdx mod
+// kListRegions, one atomic per wave.  A workgroup of kBlock threads appends
+// at most kBlock entries, so a region holds those of at most clist_cap /
+// kBlock workgroups.
+__device__ __forceinline__ void append_claimer(const Dev& d, uint32_t entry)
+{
+    const uint32_t r = blockIdx.x & (kListRegions - 1u);
+    const uint32_t k = wave_append(&d.ccount[r * kListStride], true);
+    d.clist[r * d.clist_cap + k] = entry;
+}
+
 // ---------------------------------------------------------------------------
 // move: O2 (event draw), O3 (Brownian step), O4 (boundaries), O5 and the
 // unimolecular part of O8, then the cell key of the moved position and the
@@ -418,6 +430,7 @@ __device__ __forceinline__ bool move_agent(const Dev& d, const Tables& T, const 
         const bool wide = T.stencil8 && (F.rmax + float(moved) * F.dmax) * T.inv_h > 0.495f;
         A.rec[i] = make_rec(fx, fy, fz, meta | (claim ? kMetaClaimer : 0u));
         d.sclaim[i] = claim ? (wide ? 2 : 1) : 0;
+        if (!B && claim && d.list_mode) append_claimer(d, i | (wide ? kListWide : 0u));
         if (record) {
             d.rkey[i] = linear_cell(T, cell_of(T, fx, fy, fz));
             d.revent[i] = ev >= 0 ? uint8_t(ev) : kNoEvent;
@@ -928,6 +941,7 @@ __device__ __forceinline__ void scatter_slot(const Dev& d, int p, int record, ui
     O.rec[j] = r;
     O.id[j] = A.id[i];
     d.sclaim[j] = claim ? 1 : 0;
+    if (!B && claim && d.list_mode) append_claimer(d, j);
     if (d.link) d.nxt[j] = kUnlinked;  // binned: in no extra chain
     if (record) {
         if (B) {
@@ -1114,7 +1128,12 @@ __device__ __forceinline__ void reduce_best(Best& b, int w, int top)
 // contact radius plus its targets' moves since the binning exceed the
 // 8-cell stencil's reach of half a cell, less 1 %, as move decided when it
 // flagged the claimer).  Groups are at least half as wide as the stencil.
-template <bool B>
+// Sl (the claimer list's search, groups of 16 to 64 lanes): a group at
+// least as wide as the stencil rounded up to a power of two (8, or 32 for
+// 27 cells) gives each cell width / 8 (or width / 32) lanes, which take
+// every (width / 8)-th (or (width / 32)-th) of its candidates, so a crowded
+// cell is scanned by several lanes; narrower groups keep two cells per lane.
+template <bool B, bool Sl = false>
 __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, const PairLds& P,
                                                const Agents& A, uint32_t t, uint32_t j,
                                                const uint4& rj, uint32_t ida, int li, int width,
@@ -1179,24 +1198,40 @@ __device__ __forceinline__ void search_claimer(const Dev& d, const Tables& T, co
         if (d.link) hd = d.head[cell];
     };
     uint32_t k0, e0, k1, e1, h0, h1;
-    range(li, k0, e0, h0);
-    range(li + width, k1, e1, h1);
+    // lane li's cells m0 and m1 (m1 none for a sliced lane), its first
+    // candidate's offset in them and the stride between its candidates
+    int m0 = li, m1 = li + width;
+    uint32_t slice = 0, stride = 1;
+    if (Sl) {
+        const int npad = wide ? 32 : 8;
+        if (width >= npad) {
+            m0 = li & (npad - 1);
+            m1 = 1 << 30;
+            slice = uint32_t(li / npad);
+            stride = uint32_t(width / npad);
+        }
+    }
+    range(m0, k0, e0, h0);
+    range(m1, k1, e1, h1);
+    k0 += slice;
+    k1 += slice;
+    if (Sl && slice) h0 = h1 = kEnd;  // a cell's first lane walks its extra chain
     Best b{kNone, 0u, 0.0f, -1};
     // up to two candidates of each cell per round, all four records
     // requested together
     while (k0 < e0 || k1 < e1) {
-        const bool a0 = k0 < e0, a1 = k0 + 1 < e0, b0 = k1 < e1, b1 = k1 + 1 < e1;
+        const bool a0 = k0 < e0, a1 = k0 + stride < e0, b0 = k1 < e1, b1 = k1 + stride < e1;
         uint4 r0{}, r1{}, r2{}, r3{};
         if (a0) r0 = A.rec[k0];
-        if (a1) r1 = A.rec[k0 + 1];
+        if (a1) r1 = A.rec[k0 + stride];
         if (b0) r2 = A.rec[k1];
-        if (b1) r3 = A.rec[k1 + 1];
+        if (b1) r3 = A.rec[k1 + stride];
         if (a0) consider<B>(T, P, A, r0, k0, j, s, x, y, z, comp, r2max, b);
-        if (a1) consider<B>(T, P, A, r1, k0 + 1, j, s, x, y, z, comp, r2max, b);
+        if (a1) consider<B>(T, P, A, r1, k0 + stride, j, s, x, y, z, comp, r2max, b);
         if (b0) consider<B>(T, P, A, r2, k1, j, s, x, y, z, comp, r2max, b);
-        if (b1) consider<B>(T, P, A, r3, k1 + 1, j, s, x, y, z, comp, r2max, b);
-        k0 += 2;
-        k1 += 2;
+        if (b1) consider<B>(T, P, A, r3, k1 + stride, j, s, x, y, z, comp, r2max, b);
+        k0 += 2 * stride;
+        k1 += 2 * stride;
     }
     if (d.link) {
         // agents placed since the binning: the cells' extra chains, and the
@@ -1343,6 +1378,90 @@ k_propose(Dev d, int p, uint32_t split, int bin, uint32_t moved, uint32_t search
     for (uint32_t q = threadIdx.x; q < np; q += kPropBlock) d.plist[pbase + q] = plocal[q];
 }
 
+// The search over the claimer list (single simulations in list mode): the
+// regions' counts give the step's n claimers; every claimer gets a group of
+// L lanes, the widest power of two from 16 to 64 with n x L within the
+// grid's lanes (so sparse claimers in crowded cells are searched by whole
+// waves), and the groups are dealt over the workgroups in turn.  The
+// proposals join the step's list as in the chunked search.
+__global__ void __launch_bounds__(kPropBlock) __attribute__((amdgpu_waves_per_eu(8)))
+k_propose_list(Dev d, int p, int bin, uint32_t moved, uint32_t search_blocks)
+{
+    __shared__ uint4 plocal[kPropLds];
+    __shared__ PairLds P;
+    __shared__ uint32_t rstart[kListRegions + 1];
+    __shared__ uint32_t nprop, pbase;
+    if (blockIdx.x >= search_blocks) {
+        sort_birth_runs(d, p, blockIdx.x - search_blocks, gridDim.x - search_blocks);
+        return;
+    }
+    static_assert(kListRegions == 64, "one lane per region in the first wave");
+    if (threadIdx.x < kListRegions) {
+        // first claimer of each region in the step's order: a wave prefix
+        const uint32_t c = d.ccount[threadIdx.x * kListStride];
+        uint32_t incl = c;
+        const int lane = lane_id();
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        rstart[threadIdx.x + 1] = incl;
+        if (threadIdx.x == 0) {
+            rstart[0] = 0;
+            nprop = 0;
+        }
+    }
+    __syncthreads();
+    const uint32_t n = rstart[kListRegions];
+    const uint32_t per0 = kPropBlock / 64u;  // groups of 64 per workgroup
+    if (blockIdx.x * per0 >= n) return;      // no claimer for this workgroup at any width
+    const Tables& T = *d.tab;
+    {
+        const uint32_t nw = uint32_t(T.ns) * (kMaxSpecies / 4);
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(&T.rule_of[0][0]);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(P.rule_of);
+        for (uint32_t q = threadIdx.x; q < nw; q += kPropBlock) dst[q] = src[q];
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.nr); q += kPropBlock) P.r2[q] = T.rule[q].r2;
+        for (uint32_t q = threadIdx.x; q < uint32_t(T.ns); q += kPropBlock) {
+            P.r2max[q] = T.claim_r2max[q];
+            P.rmax[q] = T.claim_rmax[q];
+            P.dmax[q] = T.claim_dmax[q];
+        }
+    }
+    __syncthreads();
+    const uint32_t t = d.ctl->s[p].t;
+    const uint32_t n_glob = d.link ? d.ctl->n_glob : 0u;
+    const Agents A = d.a[p ^ 1];
+    uint32_t L = 64;
+    while (L > 16 && uint64_t(n) * L > uint64_t(search_blocks) * kPropBlock) L >>= 1;
+    const uint32_t per = kPropBlock / L;  // groups per workgroup
+    const int li = int(threadIdx.x & (L - 1u));
+    // every lane of a group takes the same claimers, so a group's shuffles
+    // stay among lanes that run them together
+    for (uint32_t q = blockIdx.x * per + threadIdx.x / L; q < n; q += search_blocks * per) {
+        // the region holding claimer q: the last with rstart <= q (regions
+        // before it may be empty; q < n keeps it below the end)
+        uint32_t r = 0;
+#pragma unroll
+        for (uint32_t h = kListRegions / 2; h; h >>= 1)
+            if (rstart[r + h] <= q) r += h;
+        const uint32_t e = d.clist[r * d.clist_cap + (q - rstart[r])];
+        const uint32_t j = e & ~kListWide;
+        const uint4 rj = A.rec[j];
+        const uint32_t ida = A.id[j];
+        search_claimer<false, true>(d, T, P, A, t, j, rj, ida, li, int(L), int(L),
+                                    (e & kListWide) != 0u, moved, n_glob, plocal, &nprop,
+                                    &d.ctl->n_prop[p]);
+    }
+    __syncthreads();
+    const uint32_t np = nprop < kPropLds ? nprop : kPropLds;
+    if (np == 0) return;
+    if (threadIdx.x == 0) pbase = atomicAdd(&d.ctl->n_prop[p], np);
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < np; q += kPropBlock) d.plist[pbase + q] = plocal[q];
+}
+
 // ---------------------------------------------------------------------------
 // finish: O7 confirmation and O8 pair products (only the claimer of a
 // confirmed pair writes, and of a mutual homotypic pair only the lower id).
@@ -1365,6 +1484,10 @@ __global__ void __launch_bounds__(kBlock) k_finish(Dev d, int p, int record, int
     uint4 e = q < d.slots ? d.plist[q] : uint4{};
     const uint32_t np = ctl->n_prop[p];
     const uint32_t t = ctl->s[p].t;
+    // the claimer list's counters start the next step at zero (this step's
+    // search has read them)
+    if (d.list_mode && blockIdx.x == prop_blocks && threadIdx.x < kListRegions)
+        d.ccount[threadIdx.x * kListStride] = 0u;
     if (!bin) {
         // a step that keeps the binning places its children here (a few by
         // the last workgroup, many by all) and does its bookkeeping
@@ -1626,6 +1749,11 @@ void launch_propose(const Dev& d, int p, int bin, uint32_t moved, hipStream_t s,
     const unsigned search = chunks * split;
     const unsigned core = chunks_for(d.capacity) * split;
     const unsigned grid = search + (bin ? 0u : d.birth_blocks);
+    if (d.list_mode) {
+        go(k_propose_list, d.list_blocks + (bin ? 0u : d.birth_blocks), kPropBlock, s, ev, d, p,
+           bin, moved, d.list_blocks);
+        return;
+    }
     if (d.n_sims > 1)
         go(k_propose<true>, grid, kPropBlock, s, ev, d, p, split, bin, moved, search, core);
     else go(k_propose<false>, grid, kPropBlock, s, ev, d, p, split, bin, moved, search, core);
