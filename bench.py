@@ -113,9 +113,9 @@ LANE_OP_PEAK = 256 * 64 * 2.4e9
 # WRITE x1.0).  Valid only for the kernel sources it was taken on (SHA-256
 # of the three files below); reported as null otherwise.
 TRAFFIC = {"fetch_scale": 2.000, "write_scale": 1.000,
-           "sources_sha256": "4388d51374a62e58b02337f2dbf1db89b57d7d2141ff35d051d49ed6b6e697b0",
+           "sources_sha256": "7ff8f4adf4cdbce2b23006fe2249d530852b600622d130249d4b9b0c78dd29e1",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19624.0, 40071.2), "scan": (4636.2, 16416.1), "scatter": (34455.6, 56195.2), "propose": (17713.6, 2952.5), "finish": (172.9, 0.5)}}
+           "kib": {"move": (19628.4, 40071.6), "scan": (4633.8, 16416.1), "scatter": (34504.9, 56202.1), "propose": (17703.7, 2952.8), "finish": (164.3, 0.5)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
@@ -332,6 +332,15 @@ def run_sweep(args, torch, mabm, W, tune_batch: bool, serial_all: bool) -> dict:
     batch.grid()  # finalize: tables, placement
     ms_batch, updates = timed_steps(torch, batch, steps)
     batch_digest = batch.digest()
+    # what launching costs at this size: the same batch's kernels timed one by
+    # one (dispatch-stamped events, direct launches) over 200 more steps,
+    # against the graph-replayed step
+    batch.profile(True)
+    batch.step(200)
+    busy_ms = sum(ms for _, ms in batch.profile_read().values()) / 200
+    batch.profile(False)
+    batch.close()
+    del batch
     sample = list(range(n)) if serial_all else \
         list(range(0, n, max(1, n // args.sweep_sample)))[:args.sweep_sample]
     log(f"c4: {len(sample)} simulations one at a time")
@@ -356,7 +365,9 @@ def run_sweep(args, torch, mabm, W, tune_batch: bool, serial_all: bool) -> dict:
                        "min_workgroups": tuned.min_workgroups,
                        "ms_per_step": {k: round(v, 4) for k, v in tuned.ms_per_step.items()}}},
         "batched": {"ms": ms_batch, "agent_updates_per_s": updates / (ms_batch * 1e-3),
-                    "launch": "graph-replayed steps (16 or more per graph launch)"},
+                    "launch": "graph-replayed steps (16 or more per graph launch)",
+                    "kernel_us_per_step": busy_ms * 1e3,
+                    "launch_gap_fraction": max(0.0, 1.0 - busy_ms / (ms_batch / steps))},
         "serial": {"value": serial, "unit": "sims/s", "ms": ms_serial_all,
                    "sims_run": len(sample),
                    "how": "every simulation run alone" if len(sample) == n else
