@@ -208,11 +208,15 @@ def timed_steps(torch, sim, steps: int):
     return ev0.elapsed_time(ev1), sim.agent_updates() - u0
 
 
-def run_single(args, torch, mabm, W, model, steps: int, warmup: int, profile: bool) -> dict:
+def run_single(args, torch, mabm, W, model, steps: int, warmup: int, profile: bool,
+               tuned=None) -> dict:
     """agent-updates/s of one simulation over ``steps`` steps after
-    ``warmup``; with ``profile``, a second region of the same length with
+    ``warmup`` (with the tuner's launch shape and search mode when
+    ``tuned``); with ``profile``, a second region of the same length with
     per-kernel durations, and the roofline of the dominant kernel."""
     sim = mabm.Sim(model, graphs=args.graph, cell_um=args.cell_um)
+    if tuned is not None:
+        tuned.apply(sim)
     G, h = sim.grid()
     sim.step(warmup)
     sim.counts()  # synchronises; surfaces any device error
@@ -531,18 +535,20 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tuned = None
+    tuned, tr = None, None
     if args.tune:
         from paper_2606_14603_amd import tune
         tr = tune.tune_cell(model)
         args.cell_um = tr.cell_um
-        tuned = {f"{h:.5f}": round(ms, 4) for h, ms in tr.ms_per_step.items()}
+        tuned = {"ms_per_step_by_cell_um": {f"{h:.5f}": round(ms, 4) for h, ms in tr.ms_per_step.items()},
+                 "lanes": tr.lanes, "min_workgroups": tr.min_workgroups, "mode": tr.mode,
+                 "ms_per_step_by_mode": {str(k): round(v, 4) for k, v in tr.ms_per_mode.items()}}
     log(f"{model.name}: {model.n_agents} agents, {args.warmup} warm-up + {args.steps} timed steps")
     r, sim = run_single(args, torch, mabm, W, model, args.steps, args.warmup,
-                        profile=not args.no_profile)
+                        profile=not args.no_profile, tuned=tr)
     config = {"workload": describe(model), "agents": model.n_agents, "grid": r.pop("grid"),
               "cell_um": r.pop("cell_um"), "graphs": args.graph, "bin_every": r.pop("bin_every"),
-              "final_step": r.pop("final_step"), "tuned_ms_per_step": tuned,
+              "final_step": r.pop("final_step"), "tuned": tuned,
               "live_agents_end": r.pop("live_agents_end")}
     line = base_line(r.pop("value"), "agent-updates/s", r.pop("steps"), r.pop("warmup"),
                      r.pop("ms_per_step"), config)

@@ -81,12 +81,16 @@ class TuneResult:
     lanes: int = 0              # 0: the library's choice
     min_workgroups: int = 0     # 0: the library's choice
     ms_per_shape: Dict[Tuple[int, int], float] = field(default_factory=dict)
+    mode: int = 0               # search mode (0: the library's choice)
+    ms_per_mode: Dict[int, float] = field(default_factory=dict)
 
     def apply(self, sim) -> None:
-        """Set the tuned launch shape on a simulation built at ``cell_um``."""
-        from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+        """Set the tuned launch shape and search mode on a simulation built
+        at ``cell_um``."""
+        from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS, PARAM_PROPOSE_MODE
         sim.set_param(PARAM_PROPOSE_LANES, self.lanes)
         sim.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, self.min_workgroups)
+        sim.set_param(PARAM_PROPOSE_MODE, self.mode)
 
 
 def shapes(cell_um: float, model) -> List[Tuple[int, int]]:
@@ -99,12 +103,14 @@ def shapes(cell_um: float, model) -> List[Tuple[int, int]]:
     return [(0, 0), (2 * lanes, 0), (0, 512), (0, 8192)]
 
 
-def _time(model, cell_um: float, shape: Tuple[int, int], steps: int, warm: int) -> float:
+def _time(model, cell_um: float, shape: Tuple[int, int], steps: int, warm: int,
+          mode: int = 0) -> float:
     import torch
-    from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS
+    from . import PARAM_PROPOSE_LANES, PARAM_PROPOSE_MIN_WORKGROUPS, PARAM_PROPOSE_MODE
     sim = Sim(model, cell_um=cell_um)
     sim.set_param(PARAM_PROPOSE_LANES, shape[0])
     sim.set_param(PARAM_PROPOSE_MIN_WORKGROUPS, shape[1])
+    sim.set_param(PARAM_PROPOSE_MODE, mode)
     sim.step(warm)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -121,8 +127,9 @@ def tune_cell(model, steps: int = 20, warm: int = 5, cache_path: Optional[str] =
               launch_shape: bool = True) -> TuneResult:
     """Fastest cell size for ``model`` among ``candidates``, then (with
     ``launch_shape``) the fastest neighbour-search launch shape among
-    ``shapes`` at that cell size; ms per step measured with HIP events on
-    each trial's stream."""
+    ``shapes`` at that cell size, then the faster search mode (per chunk
+    or over the claimer list) at that shape; ms per step measured with HIP
+    events on each trial's stream."""
     key = shape_key(model)
     if cache_path and not _CACHE and os.path.exists(cache_path):
         with open(cache_path) as f:
@@ -130,20 +137,27 @@ def tune_cell(model, steps: int = 20, warm: int = 5, cache_path: Optional[str] =
     if key in _CACHE:
         c = _CACHE[key]
         if isinstance(c, dict):
-            return TuneResult(c["cell_um"], {}, True, c.get("lanes", 0), c.get("min_workgroups", 0))
+            return TuneResult(c["cell_um"], {}, True, c.get("lanes", 0), c.get("min_workgroups", 0),
+                              mode=c.get("mode", 0))
         return TuneResult(float(c), {}, cached=True)
     timings = {h: _time(model, h, (0, 0), steps, warm) for h in candidates(model)}
     best = min(timings, key=timings.get)
     per_shape = {(0, 0): timings[best]}
+    per_mode: Dict[int, float] = {}
+    mode = 0
     if launch_shape:
         for sh in shapes(best, model)[1:]:
             per_shape[sh] = _time(model, best, sh, steps, warm)
     lanes, minwg = min(per_shape, key=per_shape.get)
-    _CACHE[key] = {"cell_um": best, "lanes": lanes, "min_workgroups": minwg}
+    if launch_shape and any(r.kind == 0 for r in model.rules):
+        # both searches at the chosen shape (the list ignores the shape)
+        per_mode = {m: _time(model, best, (lanes, minwg), steps, warm, m) for m in (1, 2)}
+        mode = min(per_mode, key=per_mode.get)
+    _CACHE[key] = {"cell_um": best, "lanes": lanes, "min_workgroups": minwg, "mode": mode}
     if cache_path:
         with open(cache_path, "w") as f:
             json.dump(_CACHE, f, indent=1, sort_keys=True)
-    return TuneResult(best, timings, False, lanes, minwg, per_shape)
+    return TuneResult(best, timings, False, lanes, minwg, per_shape, mode, per_mode)
 
 
 @dataclass

@@ -64,11 +64,15 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run_pair(model, checkpoints, record=True, cell_um=None, search="cells", importer=None):
-    """Step both sides to each checkpoint and compare the full export."""
+def run_pair(model, checkpoints, record=True, cell_um=None, search="cells", importer=None,
+             params=None):
+    """Step both sides to each checkpoint and compare the full export;
+    ``params`` ({parameter: value}) are set on the library's simulation."""
     import paper_2606_14603_amd as mabm
     say(f"[parity] {model.name} n={model.n_agents} checkpoints={checkpoints}")
     g = mabm.Sim(model, record=record, cell_um=cell_um)
+    for k, v in (params or {}).items():
+        g.set_param(k, v)
     if importer is not None:
         importer(g)
     G, _ = g.grid()

@@ -5,7 +5,8 @@ probabilities of 0 and 1) and unimolecular rules of every placement
 enough that many placements are rejected near walls and membranes,
 translocations both ways), dense enough that claims conflict.  The GPU must
 match the oracle bit for bit on every one, with the cell lists kept between
-binnings as the library chooses and with binning every step."""
+binnings as the library chooses and with binning every step, and with the
+neighbour search per chunk and over the claimer list."""
 import numpy as np
 import pytest
 
@@ -97,6 +98,14 @@ def test_random_models_match_oracle(seed):
     run_pair(m, [1, 2, 5, 12, 25])
 
 
+@pytest.mark.parametrize("seed", range(24))
+def test_random_models_in_list_mode(seed):
+    # the same random models with the neighbour search over the claimer list
+    import paper_2606_14603_amd as mabm
+    m = random_model(seed)
+    run_pair(m, [1, 2, 5, 12, 25], params={mabm.PARAM_PROPOSE_MODE: 2})
+
+
 @pytest.mark.parametrize("seed", [100, 101, 102])
 def test_random_models_binning_every_step(seed):
     import paper_2606_14603_amd as mabm
@@ -164,6 +173,7 @@ def test_random_larger_models_and_launch_shapes(seed):
     g = mabm.Sim(m, record=True, cell_um=cell, graphs=bool(rng.random() < 0.5))
     g.set_param(mabm.PARAM_PROPOSE_LANES, int(rng.choice([0, 8, 16])))
     g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, int(rng.choice([0, 256, 4096])))
+    g.set_param(mabm.PARAM_PROPOSE_MODE, int(rng.choice([0, 1, 2])))
     G, _ = g.grid()
     o = oracle.OracleSim(m, grid_n=G)
     done = 0
