@@ -72,14 +72,14 @@ PAPER_CONTEXT = ("paper: no agent-updates/s published; 8 h of simulated time too
 KERNEL_BYTES = {"move": (40, 0, 0), "scan": (0, 0, 12), "scatter": (49, 0, 0),
                 "propose": (1, 88, 0), "finish": (0, 0, 0)}
 MOVE_KEPT_BYTES = 37
-# The survey's algorithmic bytes, independent of this library's layout:
+# Algorithmic bytes independent of this library's layout:
 # 17 B of agent state per agent (three float positions, a 4-byte id, a
 # species byte); move reads it and writes it once (34 B per agent), and a
 # whole step moves 70 B per agent-update (state read and written, cell key
 # written and read, permutation, claim slot reset and confirm, cell tables
 # at about one cell per agent).
-SURVEY_MOVE_BYTES = 34
-SURVEY_STEP_BYTES = 70
+STATE_MOVE_BYTES = 34
+STATE_STEP_BYTES = 70
 
 # move is bound by vector-ALU issue, not by HBM.  Its algorithmic work is
 # the arithmetic the step definition prescribes per agent, each 32-bit
@@ -105,7 +105,7 @@ MOVE_OPS_KEPT = 226
 # library is built without packed fp32.)
 LANE_OP_PEAK = 256 * 64 * 2.4e9
 
-# HBM traffic of the step kernels per launch, builder-measured with
+# HBM traffic of the step kernels per launch, measured beforehand with
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over
 # 55 dispatches of "bench.py --steps 50 --warmup 5 --only-c2
 # --no-cpu-baseline --no-profile --copy-calib-mb 512"), scaled by what the
@@ -263,21 +263,21 @@ def run_single(args, torch, mabm, W, model, steps: int, warmup: int, profile: bo
     ops = live * (MOVE_OPS_BIN * bin_launches + MOVE_OPS_KEPT * (mv["launches"] - bin_launches)) \
         / mv["launches"]
     achieved = ops / (us * 1e-6)
-    survey_move = SURVEY_MOVE_BYTES * live
+    state_move = STATE_MOVE_BYTES * live
     roof = {"bound": "alu", "kernel": "move", "achieved": round(achieved / 1e12, 2),
             "peak": round(LANE_OP_PEAK / 1e12, 2), "unit": "T lane-op/s",
             "frac": round(achieved / LANE_OP_PEAK, 4),
             "traffic": mv.get("traffic_bytes"),
-            "traffic_note": "builder-measured FETCH_SIZE+WRITE_SIZE per launch, null unless "
-                            "the kernel sources match the counters' SHA-256",
+            "traffic_note": "FETCH_SIZE+WRITE_SIZE per launch from a stored rocprofv3 counter "
+                            "run, null unless the kernel sources match its SHA-256",
             "alg_ops_per_launch": int(ops),
-            "hbm": {"alg_bytes_per_launch": int(survey_move),
-                    "achieved_gbs": round(survey_move / us / 1e3, 1), "peak_gbs": HBM_PEAK_GBS,
-                    "frac": round(survey_move / us / 1e3 / HBM_PEAK_GBS, 4)}}
-    # the whole step against the HBM roofline of the survey's 70 B per update
-    step_gbs = SURVEY_STEP_BYTES * value / 1e9
-    roof["step"] = {"alg_bytes_per_update": SURVEY_STEP_BYTES, "alg_gbs": round(step_gbs, 1),
-                    "hbm_roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / SURVEY_STEP_BYTES,
+            "hbm": {"alg_bytes_per_launch": int(state_move),
+                    "achieved_gbs": round(state_move / us / 1e3, 1), "peak_gbs": HBM_PEAK_GBS,
+                    "frac": round(state_move / us / 1e3 / HBM_PEAK_GBS, 4)}}
+    # the whole step against the HBM roofline of 70 B per update
+    step_gbs = STATE_STEP_BYTES * value / 1e9
+    roof["step"] = {"alg_bytes_per_update": STATE_STEP_BYTES, "alg_gbs": round(step_gbs, 1),
+                    "hbm_roofline_updates_per_s": HBM_PEAK_GBS * 1e9 / STATE_STEP_BYTES,
                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)}
     roof["copy_ceiling_gbs"] = round(copy_ceiling_gbs(torch), 1)
     out.update(roofline=roof, kernels=kernels, ms_per_step_kernel_timed=ms_direct / steps)
