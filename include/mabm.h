@@ -345,8 +345,9 @@ mabm_status mabm_ring_read(mabm_sim* sim, uint64_t* out, uint32_t max_entries,
  * the kernel that flags them, every claimer getting 16 to 64 lanes as the
  * list's length allows and a stencil cell's candidates shared by several of
  * them (for sparse claimers in crowded cells); single simulations only
- * (E_INVALID for a batch).  0 (default): 2 when the claimer species hold
- * under 1/64 of the initial agents of a single simulation, else 1.
+ * (E_INVALID for a batch).  0 (default): 2 for a single simulation whose
+ * claimer species hold under 1/64 of its initial agents or at most 32,768
+ * of them, else 1.
  * mabm_get_param returns the mode in use, 1 or 2 (finalizes the model). */
 #define MABM_PARAM_PROPOSE_MODE 5
 mabm_status mabm_set_param(mabm_sim* sim, int32_t param, uint32_t value);

@@ -636,8 +636,11 @@ void fill_dev(mabm_sim* s)
 // The neighbour search's mode (results do not depend on it): per chunk of
 // sorted agents, or over the claimer list (single simulations only).  The
 // list pays one atomic per wave that holds claimers when it is built, and
-// spreads few claimers in crowded cells over whole waves, so `auto` takes
-// it when claimers are under 1/64 of the initial agents.
+// deals the claimers evenly over the search's whole grid with at least 16
+// lanes each, so `auto` takes it when claimers are under 1/64 of the
+// initial agents (few claimers, often in crowded cells) or few enough to
+// get 16 lanes each in one pass of the grid (small simulations, whose
+// chunks are too few to fill the GPU).
 void set_list_mode(mabm_sim* s)
 {
     Dev& d = s->dev;
@@ -653,12 +656,12 @@ void set_list_mode(mabm_sim* s)
                 all += c;
                 if (T.claimer[k]) claimers += c;
             }
-            list = claimers > 0 && claimers * 64 < all;
+            const uint64_t one_pass = (uint64_t)kListBlocks * 256u / 16u;
+            list = claimers > 0 && (claimers * 64 < all || claimers <= one_pass);
         }
     }
     d.list_mode = list ? 1u : 0u;
-    const uint32_t wgs = (d.capacity + 255u) / 256u;
-    d.list_blocks = wgs < kListBlocks ? wgs : kListBlocks;
+    d.list_blocks = kListBlocks;
 }
 
 // first step / query / import: tables, hash geometry, upload, placement

@@ -98,12 +98,14 @@ def test_random_models_match_oracle(seed):
     run_pair(m, [1, 2, 5, 12, 25])
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("seed", range(24))
-def test_random_models_in_list_mode(seed):
-    # the same random models with the neighbour search over the claimer list
+def test_random_models_in_either_search(seed, mode):
+    # the same random models with the chunked search and over the claimer
+    # list (the automatic choice takes the list for most of these sizes)
     import paper_2606_14603_amd as mabm
     m = random_model(seed)
-    run_pair(m, [1, 2, 5, 12, 25], params={mabm.PARAM_PROPOSE_MODE: 2})
+    run_pair(m, [1, 2, 5, 12, 25], params={mabm.PARAM_PROPOSE_MODE: mode})
 
 
 @pytest.mark.parametrize("seed", [100, 101, 102])

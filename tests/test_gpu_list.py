@@ -1,11 +1,12 @@
-"""The claimer-list search (PARAM_PROPOSE_MODE = 2) on the GPU, bit for bit
-against the oracle: the kept-binning cases (both stencils, holes carried
-over kept steps, the periodic box, agents placed in extra chains and the
-global list), crowded stencils, dense claimers (groups of 16 lanes, several
-passes per workgroup), the nuclear-signalling workload over 2,000 steps,
-graph replay and the mode switched in mid-run.  The automatic choice takes
-the list for sparse claimers and the chunked search for dense ones; a batch
-refuses the list."""
+"""Both neighbour searches on the GPU, bit for bit against the oracle: the
+claimer list (PARAM_PROPOSE_MODE = 2) and the chunked search (1) on the
+kept-binning cases (both stencils, holes carried over kept steps, the
+periodic box, agents placed in extra chains and the global list), crowded
+stencils; the list with dense claimers (groups of 16 lanes, several passes
+per workgroup), over 2,000 steps of the nuclear-signalling workload, under
+graph replay; the mode switched in mid-run.  The automatic choice takes the
+list for sparse claimers and small simulations and the chunked search for
+large dense ones; a batch refuses the list."""
 import numpy as np
 import pytest
 
@@ -54,7 +55,10 @@ def test_automatic_mode():
     import paper_2606_14603_amd as mabm
     sparse = mabm.Sim(W.c3(20_000, seed=1))  # 4 genes claim among 20k agents
     assert sparse.get_param(mabm.PARAM_PROPOSE_MODE) == LIST
-    dense = mabm.Sim(W.c2(20_000, seed=1))   # about 6 % claimers
+    small = mabm.Sim(W.c1(seed=1))           # 10k claimers: 16 lanes each in one pass
+    assert small.get_param(mabm.PARAM_PROPOSE_MODE) == LIST
+    small.close()
+    dense = mabm.Sim(W.c2(600_000, seed=1))  # about 6 % claimers, 34.5k of them
     assert dense.get_param(mabm.PARAM_PROPOSE_MODE) == CHUNKS
     dense.set_param(mabm.PARAM_PROPOSE_MODE, LIST)
     assert dense.get_param(mabm.PARAM_PROPOSE_MODE) == LIST
@@ -70,24 +74,26 @@ def test_automatic_mode():
         s.close()
 
 
+@pytest.mark.parametrize("mode", [LIST, CHUNKS])
 @pytest.mark.parametrize("name,make,cell", CASES + PLACING, ids=[c[0] for c in CASES + PLACING])
-def test_list_search_over_kept_binnings(name, make, cell):
+def test_both_searches_over_kept_binnings(name, make, cell, mode):
     import paper_2606_14603_amd as mabm
     m = make()
-    g = run_list(m, [1, 2, 3, 7, 16, 33], cell=cell)
+    g = run_list(m, [1, 2, 3, 7, 16, 33], cell=cell, mode=mode)
     k = g.get_param(mabm.PARAM_BIN_EVERY)
     assert k == expected_bin_every(m, g.grid()[0]) and k > 1
-    say(f"[list] {name} bin_every={k} ok")
+    say(f"[search {mode}] {name} bin_every={k} ok")
 
 
+@pytest.mark.parametrize("mode", [LIST, CHUNKS])
 @pytest.mark.parametrize("bin_max", [0, 1])
-def test_list_search_in_crowded_cells(bin_max):
+def test_both_searches_in_crowded_cells(bin_max, mode):
     # cells far larger than the contact radius in a dense box: hundreds of
-    # candidates per stencil, shared by a group's lanes cell by cell
+    # candidates per stencil (the list shares a cell among a group's lanes)
     import paper_2606_14603_amd as mabm
     m = W.c1(n_a=9000, n_b=9000, n_c=2000, box_um=0.9, seed=31, unbind_p=0.02)
     g = mabm.Sim(m, record=True, cell_um=0.15)
-    g.set_param(mabm.PARAM_PROPOSE_MODE, LIST)
+    g.set_param(mabm.PARAM_PROPOSE_MODE, mode)
     g.set_param(mabm.PARAM_BIN_EVERY_MAX, bin_max)
     o = oracle.OracleSim(m, grid_n=g.grid()[0])
     done = 0
@@ -99,10 +105,10 @@ def test_list_search_in_crowded_cells(bin_max):
 
 
 def test_dense_claimers_take_several_passes():
-    # half the agents claim: groups of 16 lanes, each workgroup searching
-    # several groups' worth of claimers in turn
-    m = W.c1(n_a=6000, n_b=6000, box_um=0.7, seed=44, unbind_p=0.05)
-    run_list(m, [1, 2, 5, 20, 60], cell=0.07)
+    # 40k claimers (half the agents): groups of 16 lanes, two passes of the
+    # search's grid
+    m = W.c1(n_a=40_000, n_b=40_000, box_um=0.7 * (80 / 12) ** (1 / 3), seed=44, unbind_p=0.05)
+    run_list(m, [1, 2, 5, 20], cell=0.07)
 
 
 def test_nuclear_signalling_long_run():
