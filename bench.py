@@ -17,15 +17,16 @@ samples of the step:
   c3        the 5M-agent nested-compartment model with births, early
             (steps 50..250) and late (from step 2,000);
   c4        the dose x replicate sweep (1,024 simulations, 20k-200k agents,
-            2,000 steps) as one batch against every simulation run alone:
-            simulations/s, and each simulation's final state compared by
-            the library's state digest;
+            2,000 steps) as one batch (cell density and launch shape chosen
+            by the batch tuner first, unless --no-tune) against every
+            simulation run alone: simulations/s, and each simulation's final
+            state compared by the library's state digest;
   c5        the serving stream at its stated ranges (sizes 50k-4M agents,
             horizons 1,000-20,000 steps, Poisson arrivals): p50/p99 latency
             and simulations/s, concurrent against FIFO, final states
             compared by digest.
 --only-c2 drops c3, c4 and c5; --workload c1|c3|c4|c5 runs one of them
-alone (c4 alone also runs the batch tuner first).
+alone.
 """
 from __future__ import annotations
 
@@ -464,7 +465,7 @@ def main() -> int:
     ap.add_argument("--tune", action="store_true",
                     help="c2/c1/c3: time candidate cell sizes first and run with the fastest")
     ap.add_argument("--no-tune", action="store_true",
-                    help="--workload c4: skip the batch tuner (cell density, launch shape)")
+                    help="skip the batch tuner (cell density, launch shape) before the sweep")
     ap.add_argument("--workload", choices=("c1", "c2", "c3", "c4", "c5"), default="c2",
                     help="c2 (default): the 2M-agent cascade step (agent-updates/s, the "
                          "headline), with a late-run sample, the 5M-agent nested-compartment "
@@ -572,7 +573,7 @@ def main() -> int:
         s3.close()
         del s3
         line["c3"] = r3
-        line["c4"] = run_sweep(args, torch, mabm, W, tune_batch=False,
+        line["c4"] = run_sweep(args, torch, mabm, W, tune_batch=not args.no_tune,
                                serial_all=args.sweep_sample == 0)
         line["c5"] = run_serving(args, torch, mabm, W, args.serve_requests,
                                  args.serve_max_agents, args.serve_min_steps,
