@@ -12,24 +12,31 @@
 //            counts the same way
 //   scan     each tile (2,048 cells, or a power of two times that) adds the
 //            sums of the tiles before it, scans its counts into cell starts
-//            and clears them
+//            and clears them; extra workgroups sort the step's birth records
+//            in runs
 //   scatter  agents to cell order in the other buffer (holes and degraded
-//            agents dropped: stream compaction); one extra workgroup ranks
-//            the step's births by parent id, appends them with fresh ids and
-//            writes the next step's scalars
+//            agents dropped: stream compaction); extra workgroups place the
+//            step's children, ranked by (simulation, parent id), with fresh
+//            ids after the binned agents, and one keeps the books (live
+//            agents, capacity, next ids, the next step's scalars)
 //   propose  per workgroup, a chunk of 1,024 sorted agents (or a share of
 //            one): its claimers are compacted in LDS, 27-cell ones first,
 //            then each is searched by a group of 4 lanes (16 for 27 cells),
 //            two stencil cells per lane, for the nearest eligible partner;
-//            Bernoulli draw; handshake keys into both claim slots
+//            Bernoulli draw; handshake keys into both claim slots.  For
+//            sparse claimers or small simulations, the claimers listed by
+//            the kernel that flagged them instead, each with 16 to 64 lanes
+//            (k_propose_list)
 //   finish   over the step's proposals: confirmation and pair products
 //
 // A step that keeps the previous binning (the library allows it while no
 // agent can have moved out of reach of the cell lists it was binned in) is
 // move, propose and finish on the agents in place: move also writes the
-// claimer flags, marks removed agents as holes and chains the agents its
-// rules place into extra per-cell chains, and finish's first workgroup
-// places the step's births (chained too) and does the step's bookkeeping.
+// claimer flags, marks removed agents as holes (listed for later children
+// to refill) and chains the agents its rules place into extra per-cell
+// chains; propose's extra workgroups sort the birth runs, finish places the
+// step's children (into listed holes first, chained too) and its last
+// workgroup keeps the books.
 //
 // Cells are sorted by the Morton index of their coordinates, so the cells of
 // a neighbourhood are close in memory.  An agent is a 16-byte record
