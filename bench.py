@@ -114,9 +114,9 @@ LANE_OP_PEAK = 256 * 64 * 2.4e9
 # WRITE x1.0).  Valid only for the kernel sources it was taken on (SHA-256
 # of the three files below); reported as null otherwise.
 TRAFFIC = {"fetch_scale": 2.000, "write_scale": 1.000,
-           "sources_sha256": "7ff8f4adf4cdbce2b23006fe2249d530852b600622d130249d4b9b0c78dd29e1",
+           "sources_sha256": "74b5b17800b2dd90018f7eb50688fd069392befb39b2901cdf72e202d772b4aa",
            # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch
-           "kib": {"move": (19628.4, 40071.6), "scan": (4633.8, 16416.1), "scatter": (34504.9, 56202.1), "propose": (17703.7, 2952.8), "finish": (164.3, 0.5)}}
+           "kib": {"move": (19628.3, 40071.5), "scan": (4633.8, 16416.1), "scatter": (34512.7, 56205.0), "propose": (17700.9, 2952.1), "finish": (164.3, 0.5)}}
 KERNEL_SOURCES = ("paper_2606_14603_amd/csrc/kernels.hip",
                   "paper_2606_14603_amd/csrc/device_math.hpp",
                   "paper_2606_14603_amd/csrc/engine.hpp")
