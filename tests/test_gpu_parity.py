@@ -9,7 +9,9 @@ cells and a ragged tail (the scaled C3 to 2,000 steps, where translocated
 agents crowd the nuclear membrane and births have refilled many holes), and
 the full 2M-agent C2 and 5M-agent C3 for 20 steps in the launch
 configuration the benchmark times, then again recording cell ids, events
-and partners for the comparison at step 20.
+and partners for the comparison at step 20.  The small cases run with the
+neighbour search the library chooses (the claimer list, at their sizes)
+and with the chunked one.
 """
 import numpy as np
 import pytest
@@ -17,6 +19,8 @@ import pytest
 import oracle
 import workloads as W
 from parity import assert_same, run_pair, say
+
+from paper_2606_14603_amd import PARAM_PROPOSE_MODE as PARAM_MODE
 
 pytestmark = pytest.mark.gpu
 
@@ -30,22 +34,30 @@ def _gpu():
     mabm.lib()  # raises if the HIP library is not built
 
 
-def test_c1_small_every_step():
+# the neighbour search as the library chooses (the claimer list at these
+# sizes) and forced to the chunked search
+SEARCH = pytest.mark.parametrize("mode", [0, 1], ids=["auto", "chunks"])
+
+
+@SEARCH
+def test_c1_small_every_step(mode):
     m = W.c1(n_a=1500, n_b=1500, box_um=2.0 * (3000 / 20000) ** (1 / 3), unbind_p=2e-2)
-    run_pair(m, list(range(1, 31)) + [60, 120])
+    run_pair(m, list(range(1, 31)) + [60, 120], params={PARAM_MODE: mode})
 
 
 def test_c1_full_size_full_horizon():
     run_pair(W.c1(), [1, 2, 10, 100, 250, 500, 1000])
 
 
-def test_c2_scaled():
-    run_pair(W.c2(20_000, seed=42, steps=200), [1, 5, 50, 200])
+@SEARCH
+def test_c2_scaled(mode):
+    run_pair(W.c2(20_000, seed=42, steps=200), [1, 5, 50, 200], params={PARAM_MODE: mode})
 
 
-def test_c3_scaled_births_and_translocation():
+@SEARCH
+def test_c3_scaled_births_and_translocation(mode):
     m = W.c3(20_000, seed=12, n_genes=300)
-    run_pair(m, [1, 10, 100, 300, 800, 2000])
+    run_pair(m, [1, 10, 100, 300, 800, 2000], params={PARAM_MODE: mode})
 
 
 def test_c2_full_size_in_bench_configuration():
@@ -60,15 +72,17 @@ def test_c3_full_size_twenty_steps():
     run_pair(W.c3(), [20], record=True)
 
 
-def test_ragged_and_tiny_sizes():
+@SEARCH
+def test_ragged_and_tiny_sizes(mode):
     for n in (1, 2, 3, 255, 256, 257, 1023, 4097):
         m = W.c1(n_a=(n + 1) // 2, n_b=n // 2, box_um=0.2, unbind_p=0.05)
-        run_pair(m, [1, 7])
+        run_pair(m, [1, 7], params={PARAM_MODE: mode})
 
 
-def test_empty_simulation():
+@SEARCH
+def test_empty_simulation(mode):
     m = W.c1(n_a=0, n_b=0, box_um=1.0)
-    run_pair(m, [1, 3])
+    run_pair(m, [1, 3], params={PARAM_MODE: mode})
 
 
 def test_cell_size_does_not_change_results():
@@ -117,7 +131,8 @@ def _import_pair(agents, next_id, t=0):
     return imp
 
 
-def test_engineered_contacts_match_oracle():
+@SEARCH
+def test_engineered_contacts_match_oracle(mode):
     R = 2.0 ** -7
     A, B, C = 0, 1, 2
     m = W.Model("claims", W.PERIODIC_BOX, 1e-6, 0,
@@ -130,7 +145,7 @@ def test_engineered_contacts_match_oracle():
               (30, B, h, 0.25, 0.75), (31, A, h - 2.0 ** -8, 0.25, 0.75),
               (32, A, h + 2.0 ** -8, 0.25, 0.75),
               (33, B, h + 2.0 ** -8 + 2.0 ** -8 + 2.0 ** -9, 0.25, 0.75)]
-    run_pair(m, [1, 2], importer=_import_pair(agents, 64))
+    run_pair(m, [1, 2], importer=_import_pair(agents, 64), params={PARAM_MODE: mode})
     sp = [W.Species(n, 0.0, 0) for n in ("A", "P", "D", "X", "E", "S", "Q")]
     rules = [W.bimol(0, 0, 1, 2, R, 1.0), W.bimol(0, 3, 1, 3, R, 1.0), W.unimol(3, 3, 1.0),
              W.bimol(4, 5, 4, 6, R, 1.0)]
@@ -138,10 +153,11 @@ def test_engineered_contacts_match_oracle():
     agents2 = [(9, 0, 0.5, 0.5, 0.5), (4, 0, 0.5 + 2.0 ** -8, 0.5, 0.5),
                (6, 0, 0.25, 0.25, 0.25), (7, 3, 0.25 + 2.0 ** -8, 0.25, 0.25),
                (1, 4, 0.75, 0.75, 0.75), (2, 5, 0.75, 0.75 + 2.0 ** -8, 0.75)]
-    run_pair(m2, [1], importer=_import_pair(agents2, 16, t=9))
+    run_pair(m2, [1], importer=_import_pair(agents2, 16, t=9), params={PARAM_MODE: mode})
 
 
-def test_dense_random_contacts_match_oracle():
+@SEARCH
+def test_dense_random_contacts_match_oracle(mode):
     rng = np.random.default_rng(3)
     n, L = 3000, 0.25
     m = W.Model("dense", W.PERIODIC_BOX, 1e-6, 11,
@@ -154,10 +170,11 @@ def test_dense_random_contacts_match_oracle():
     pos = rng.uniform(0, L, (n, 3)).astype(np.float32)
     agents = [(int(i), int(s), float(p[0]), float(p[1]), float(p[2]))
               for i, s, p in zip(rng.permutation(5 * n)[:n], rng.integers(0, 2, n), pos)]
-    run_pair(m, [1, 2, 5, 20], importer=_import_pair(agents, 5 * n, t=3))
+    run_pair(m, [1, 2, 5, 20], importer=_import_pair(agents, 5 * n, t=3), params={PARAM_MODE: mode})
 
 
-def test_nested_dense_membrane_contacts():
+@SEARCH
+def test_nested_dense_membrane_contacts(mode):
     rng = np.random.default_rng(4)
     n = 4000
     m = W.Model("memb", W.NESTED_SPHERES, 1e-6, 5,
@@ -176,7 +193,7 @@ def test_nested_dense_membrane_contacts():
     p = (d * r[:, None]).astype(np.float32)
     agents = [(i, int(s), float(q[0]), float(q[1]), float(q[2]))
               for i, (s, q) in enumerate(zip(rng.integers(0, 2, n), p))]
-    run_pair(m, [1, 2, 10, 40], importer=_import_pair(agents, n))
+    run_pair(m, [1, 2, 10, 40], importer=_import_pair(agents, n), params={PARAM_MODE: mode})
 
 
 def test_graph_replay_matches_direct_launches():
@@ -208,6 +225,7 @@ def test_dense_box_overflows_the_workgroup_proposal_stage():
     m = W.c1(n_a=4000, n_b=4000, box_um=0.2, bind_p=1.0, unbind_p=0.02)
     m.seed = 77
     g = mabm.Sim(m, record=True)
+    g.set_param(mabm.PARAM_PROPOSE_MODE, 1)  # the chunked search, one workgroup per chunk
     g.set_param(mabm.PARAM_PROPOSE_MIN_WORKGROUPS, 1)
     G, _ = g.grid()
     o = oracle.OracleSim(m, grid_n=G)

@@ -94,9 +94,10 @@ def test_tuner_picks_a_candidate_and_caches_it(tmp_path):
     assert r.cell_um in r.ms_per_step and len(r.ms_per_step) == len(tune.candidates(m))
     assert (r.lanes, r.min_workgroups) in r.ms_per_shape
     assert set(r.ms_per_shape) == set(tune.shapes(r.cell_um, m))
+    assert set(r.ms_per_mode) == {1, 2} and r.mode == min(r.ms_per_mode, key=r.ms_per_mode.get)
     c = tune.tune_cell(W.c2(60_000, seed=4))
-    assert c.cached and (c.cell_um, c.lanes, c.min_workgroups) == (r.cell_um, r.lanes,
-                                                                   r.min_workgroups)
+    assert c.cached and (c.cell_um, c.lanes, c.min_workgroups, c.mode) == (
+        r.cell_um, r.lanes, r.min_workgroups, r.mode)
     say(f"[tune] {m.name}: {r.cell_um:.4f} um from {r.ms_per_step}, "
         f"shape {r.lanes, r.min_workgroups} from {r.ms_per_shape}")
 
@@ -117,6 +118,7 @@ def test_launch_shape_leaves_results_unchanged(which):
         m, cell = W.c1(n_a=3000, n_b=2500, box_um=0.5, unbind_p=2e-2), None
     shapes = [(32, 0), (4, 1 << 16), (8, 1), (16, 512), (0, 0)]
     g = mabm.Sim(m, record=True, cell_um=cell, graphs=True)
+    g.set_param(mabm.PARAM_PROPOSE_MODE, 1)  # the chunked search, which the shape steers
     G, _ = g.grid()
     o = oracle.OracleSim(m, grid_n=G)
     for k, (lanes, minwg) in enumerate(shapes):
