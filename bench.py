@@ -408,38 +408,51 @@ def run_serving(args, torch, mabm, W, n_requests: int, n_max: int, h_min: int,
     # load the code objects and the graph path once
     serve.Server(budget, max_active=2).run(W.c5_requests(2, seed=99, n_max=60_000, h_max=300),
                                            [0.0, 0.0])
-    log(f"c5: {n_requests} requests, FIFO capacity")
     fifo = serve.Server(budget, max_active=1, chunk=args.serve_chunk, progress=progress)
-    cap = serve.summarize(fifo.run(models, np.zeros(len(models))))
-    rate = 0.7 * cap["sims_per_s"]
-    arrivals = W.poisson_arrivals(len(models), rate, seed=0)
-    log(f"c5: Poisson arrivals at {rate:.3f}/s, FIFO")
-    res_fifo = fifo.run(models, arrivals)
     conc = serve.Server(budget, max_active=args.serve_active, chunk=args.serve_chunk,
                         progress=progress, fill_agents=args.serve_fill_agents)
-    log("c5: concurrent capacity")
-    cap_conc = serve.summarize(conc.run(models, np.zeros(len(models))))
-    log("c5: Poisson arrivals, concurrent")
-    res_conc = conc.run(models, arrivals)
-    s_fifo, s_conc = serve.summarize(res_fifo), serve.summarize(res_conc)
-    by_name = {r.name: r.digest for r in res_fifo}
-    same = sum(int(by_name[r.name] == r.digest) for r in res_conc)
-    return {
-        "value": s_conc["sims_per_s"], "unit": "sims/s",
-        "config": {"workload": f"c5_requests: {len(models)} requests, random closed subsets of "
-                               f"the cascade's rules, 50k-{n_max // 1000}k agents (log-uniform), "
-                               f"{h_min}-{h_max} steps (uniform), Poisson arrivals at 0.7 x the "
-                               f"FIFO capacity",
-                   "arrival_rate_per_s": rate, "budget_bytes": budget,
-                   "chunk_steps": args.serve_chunk, "max_active": args.serve_active,
-                   "fill_agents": args.serve_fill_agents},
-        "p50_s": s_conc["p50_s"], "p99_s": s_conc["p99_s"],
-        "concurrent": s_conc, "fifo": s_fifo, "fifo_capacity": cap,
-        "concurrent_capacity": cap_conc,
-        "capacity_ratio": cap_conc["sims_per_s"] / cap["sims_per_s"],
-        "identical_states": f"{same}/{len(res_conc)}",
-        "bit_identical": same == len(res_conc),
-    }
+    out = {"unit": "sims/s"}
+    pairs = []  # (FIFO results, concurrent results) of the same requests
+    cap = None
+    if args.serve_legs in ("all", "capacity"):
+        log(f"c5: {n_requests} requests, FIFO capacity")
+        res_cap_fifo = fifo.run(models, np.zeros(len(models)))
+        cap = serve.summarize(res_cap_fifo)
+        log("c5: concurrent capacity")
+        res_cap_conc = conc.run(models, np.zeros(len(models)))
+        cap_conc = serve.summarize(res_cap_conc)
+        pairs.append((res_cap_fifo, res_cap_conc))
+        out.update(fifo_capacity=cap, concurrent_capacity=cap_conc,
+                   capacity_ratio=cap_conc["sims_per_s"] / cap["sims_per_s"],
+                   value=cap_conc["sims_per_s"])
+    rate = args.serve_rate if args.serve_rate > 0 else (0.7 * cap["sims_per_s"] if cap else 0.0)
+    if args.serve_legs in ("all", "poisson"):
+        if rate <= 0:
+            raise SystemExit("--serve-legs poisson needs --serve-rate")
+        arrivals = W.poisson_arrivals(len(models), rate, seed=0)
+        log(f"c5: Poisson arrivals at {rate:.3f}/s, FIFO")
+        res_fifo = fifo.run(models, arrivals)
+        log("c5: Poisson arrivals, concurrent")
+        res_conc = conc.run(models, arrivals)
+        s_fifo, s_conc = serve.summarize(res_fifo), serve.summarize(res_conc)
+        pairs.append((res_fifo, res_conc))
+        out.update(value=s_conc["sims_per_s"], p50_s=s_conc["p50_s"], p99_s=s_conc["p99_s"],
+                   concurrent=s_conc, fifo=s_fifo)
+    same = total = 0
+    for a, b in pairs:
+        by_name = {r.name: r.digest for r in a}
+        same += sum(int(by_name[r.name] == r.digest) for r in b)
+        total += len(b)
+    out["config"] = {"workload": f"c5_requests: {len(models)} requests, random closed subsets of "
+                                 f"the cascade's rules, 50k-{n_max // 1000}k agents (log-uniform), "
+                                 f"{h_min}-{h_max} steps (uniform), Poisson arrivals at "
+                                 + ("0.7 x the FIFO capacity" if args.serve_rate <= 0 else
+                                    f"{rate:.3f}/s"),
+                     "legs": args.serve_legs, "arrival_rate_per_s": rate, "budget_bytes": budget,
+                     "chunk_steps": args.serve_chunk, "max_active": args.serve_active,
+                     "fill_agents": args.serve_fill_agents}
+    out.update(identical_states=f"{same}/{total}", bit_identical=same == total)
+    return out
 
 
 def base_line(value, unit, steps, warmup, ms_per_step, config, hib=True) -> dict:
@@ -487,6 +500,11 @@ def main() -> int:
     ap.add_argument("--serve-min-steps", type=int, default=1000, help="c5: shortest horizon")
     ap.add_argument("--serve-max-steps", type=int, default=20000, help="c5: longest horizon")
     ap.add_argument("--serve-active", type=int, default=64, help="c5: simulations admitted at once")
+    ap.add_argument("--serve-legs", choices=("all", "capacity", "poisson"), default="all",
+                    help="c5: the capacity runs (all requests at once, FIFO and concurrent), "
+                         "the Poisson runs, or both")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="c5: Poisson arrival rate (0: 0.7 x the FIFO capacity measured first)")
     ap.add_argument("--serve-budget-gb", type=float, default=0.0,
                     help="c5: HBM budget for admitted arenas (0: 85%% of free memory)")
     ap.add_argument("--sweep-reps", type=int, default=64, help="c4: replicates per dose")
