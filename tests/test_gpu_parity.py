@@ -60,6 +60,23 @@ def test_c3_scaled_births_and_translocation(mode):
     run_pair(m, [1, 10, 100, 300, 800, 2000], params={PARAM_MODE: mode})
 
 
+def test_c1_parity_grid_of_17_cells():
+    # the reversible-binding workload on a 17-cell grid (2/17 um cells, a
+    # Morton grid padded to 32 per axis) for its whole horizon
+    run_pair(W.c1(), [1, 100, 1000], cell_um=2.0 / 17 * (1 + 1e-6))
+
+
+def test_c2_scaled_full_horizon():
+    # the cascade scaled to 20k agents for the workload's 5,000 steps
+    run_pair(W.c2(20_000, seed=43), [1, 1000, 5000])
+
+
+def test_c3_scaled_full_horizon():
+    # the nuclear-signalling model scaled to 20k agents for the workload's
+    # 10,000 steps (the crowded-membrane regime, births refilling holes)
+    run_pair(W.c3(20_000, seed=13, n_genes=12), [1, 2000, 10_000], record=False)
+
+
 def test_c2_full_size_in_bench_configuration():
     # the benchmark's configuration: 2M agents, no recording, library-chosen grid
     run_pair(W.c2(), [1, 3, 20], record=False)
