@@ -122,7 +122,7 @@ def test_random_models_binning_every_step(seed):
                               b[k].view(np.uint32) if b[k].dtype == np.float32 else b[k]), k
 
 
-@pytest.mark.parametrize("seed", range(200, 210))
+@pytest.mark.parametrize("seed", range(200, 240))
 def test_random_model_batches_match_oracle(seed):
     # one random model, five simulations of it with their own seeds, volumes
     # and initial counts (one of them empty), stepped as one batch
@@ -261,3 +261,37 @@ def test_random_models_served_concurrently():
     res = serve.Server(1 << 34, max_active=4, chunk=16, record=True,
                        keep_state=True).run(models, np.zeros(len(models)))
     check_served(res, models, "random models, concurrent")
+
+
+def test_hundred_more_random_models_in_both_searches():
+    # 100 further random models (every fourth scaled to 20k-80k agents),
+    # each with the chunked search and over the claimer list; where the
+    # oracle outgrows the capacity, the library reports E_CAPACITY at the
+    # same checkpoint
+    import oracle
+    import paper_2606_14603_amd as mabm
+    from parity import assert_same
+    overflowed = 0
+    for seed in range(1000, 1100):
+        rng = np.random.default_rng(seed)
+        m = random_model(seed)
+        if seed % 4 == 0:
+            m = scaled(m, int(rng.integers(20_000, 80_000)))
+        for mode in (1, 2):
+            g = mabm.Sim(m, record=True, graphs=bool(seed % 3 == 0))
+            g.set_param(mabm.PARAM_PROPOSE_MODE, mode)
+            o = oracle.OracleSim(m, grid_n=g.grid()[0])
+            done = 0
+            for c in (1, 6, 30):
+                g.step(c - done)
+                try:
+                    o.step(c - done)
+                except oracle.OracleError:
+                    with pytest.raises(mabm.MabmError) as err:
+                        g.counts()
+                    assert err.value.code == mabm.E_CAPACITY
+                    overflowed += 1
+                    break
+                done = c
+                assert_same(g.export(), o.export(), f"{m.name} mode {mode} t={c}")
+    assert overflowed <= 8
